@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Throughput of the motion-vector warp on one MI355X.
+
+One step = the whole hot path over one batch: the fused K-phase forward warp
+(output frames, validity mask, invalid counts) followed by the adjoint
+(image and motion gradients) for the same batch. Default workload: 8 frames
+of 1920x1080 RGBA stored as float32, pan + 16 moving rectangles, 3 phases
+(1/4, 2/4, 3/4). Inputs are resident in device memory before timing starts;
+two complete buffer sets alternate between steps so that one step's data is
+not served from the previous step's caches.
+
+Prints one JSON line. ``value`` = output pixels (N*K*H*W) per second of a
+forward+backward step, in Mpix/s.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+KERNEL_SRC = os.path.join(ROOT, "paper_2307_12607_amd", "csrc", "warp_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=30)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
+    p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    p.add_argument("--no-variants", action="store_true", help="skip the FP16 / 4K lines")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run a plain 1 GiB device copy first (for counter scaling)")
+    return p.parse_args()
+
+
+def algorithmic_bytes(n, c, h, w, k, b):
+    """Bytes the method must move once per launch (each input read once, each
+    output written once)."""
+    px = n * h * w
+    fwd = px * c * b + px * 8 + px * k * c * b + px * k * 1 + n * k * 4
+    bwd = px * k * c * b + px * c * b + px * 8 + px * c * b + px * 8
+    return fwd, bwd
+
+
+def source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from stored rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != source_sha():
+        return None
+    entry = rec.get("kernels", {}).get(f"{kernel}|{workload}")
+    if not entry:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+class Workload:
+    def __init__(self, index, dtype, dev, sets=2):
+        import torch
+        from synth import make_config
+
+        self.torch = torch
+        d = make_config(index)
+        self.spec = d["spec"]
+        self.dtype = dtype
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+        self.phases = [float(s) for s in d["phases"]]
+        n, c, h, w = d["src"].shape
+        k = len(self.phases)
+        self.shape = (n, c, h, w, k)
+        src = torch.from_numpy(d["src"]).to(dev).to(tdt)
+        mv = torch.from_numpy(d["mv"]).to(dev)
+        gen = torch.Generator(device=dev).manual_seed(1234)
+        self.sets = []
+        for i in range(sets):
+            s = {
+                "src": src if i == 0 else src.clone(),
+                "mv": mv if i == 0 else mv.clone(),
+                "out": torch.empty((n, k, c, h, w), dtype=tdt, device=dev),
+                "mask": torch.empty((n, k, h, w), dtype=torch.uint8, device=dev),
+                "count": torch.empty((n, k), dtype=torch.int32, device=dev),
+                # upstream gradient dL/d out (stands in for a loss gradient)
+                "gout": torch.randn((n, k, c, h, w), device=dev, generator=gen).to(tdt),
+                "gsrc": torch.empty((n, c, h, w), dtype=tdt, device=dev),
+                "gmv": torch.empty((n, 2, h, w), dtype=torch.float32, device=dev),
+            }
+            import paper_2307_12607_amd as exw
+            nb = exw.exw_warp_backward_workspace_bytes(tdt, n, c, h, w)
+            s["ws"] = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+            self.sets.append(s)
+        self.b = 4 if dtype == "f32" else 2
+        self.fwd_bytes, self.bwd_bytes = algorithmic_bytes(n, c, h, w, k, self.b)
+        self.out_px = n * k * h * w
+
+    def name(self):
+        n, c, h, w, k = self.shape
+        return f"config{self.spec.index}: {n}x{w}x{h} C={c} K={k} {self.dtype}"
+
+    def run(self, steps, warmup):
+        import paper_2307_12607_amd as exw
+        torch = self.torch
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+
+        def step(i, ev=None):
+            s = self.sets[i % len(self.sets)]
+            if ev:
+                ev[0].record()
+            exw.exw_warp_forward_batched(s["src"], s["mv"], self.phases, s["out"], s["mask"],
+                                         s["count"])
+            if ev:
+                ev[1].record()
+            exw.exw_warp_backward_batched(s["src"], s["mv"], self.phases, s["gout"], s["gsrc"],
+                                          s["gmv"], s["ws"])
+            if ev:
+                ev[2].record()
+
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(warmup + i, evs[i])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        fwd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+        bwd_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+        ms = 1e3 * elapsed / steps
+        return {
+            "ms_per_step": ms,
+            "fwd_ms": fwd_ms,
+            "bwd_ms": bwd_ms,
+            "mpix_s": self.out_px / (ms * 1e-3) / 1e6,
+            "fwd_mpix_s": self.out_px / (fwd_ms * 1e-3) / 1e6,
+            "fwd_gbs": self.fwd_bytes / (fwd_ms * 1e-3) / 1e9,
+            "bwd_gbs": self.bwd_bytes / (bwd_ms * 1e-3) / 1e9,
+        }
+
+    def free(self):
+        self.sets = []
+        self.torch.cuda.empty_cache()
+
+
+def copy_ceiling(dev, nbytes=1 << 30, reps=5):
+    """GB/s of a plain device-to-device copy (read + write counted)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(index, budget_s=20.0):
+    """The float64 C oracle (as it stands) on the host cores: forward + backward
+    over a bounded sample of the same workload (its first frames)."""
+    import numpy as np
+    from oracle import ref_c
+    from synth import make_config
+
+    threads = min(os.cpu_count() or 1, 16)
+    ref_c.set_threads(threads)
+    d = make_config(index, n=1)
+    s, m, ph = ref_c.prepare(d["src"], d["mv"], d["phases"])
+    n, c, h, w = s.shape
+    k = ph.size
+    out = np.empty((n, k, c, h, w))
+    mask = np.empty((n, k, h, w), np.uint8)
+    cnt = np.empty((n, k), np.int64)
+    g = np.random.default_rng(0).standard_normal((n, k, c, h, w))
+    gs = np.empty_like(s)
+    gm = np.empty((n, 2, h, w))
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        ref_c.forward_prepared(s, m, ph, out, mask, cnt)
+        ref_c.backward_prepared(s, m, ph, g, gs, gm)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s / max(threads, 1) or reps >= 50:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": round(n * k * h * w / dt / 1e6, 3), "unit": "Mpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"float64 C oracle, forward+backward of 1 frame of the workload "
+                      f"({w}x{h}, C={c}, K={k}), {reps} reps, {threads} OpenMP threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the warp's frames and "
+              "phases are independent, so N GPUs would each run this same step on their own "
+              "batch.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2307_12607_amd  # noqa: F401  (fails loudly if the HIP library is missing)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        copy_ceiling(dev, reps=3)
+
+    main_wl = Workload(args.config, args.dtype, dev)
+    r = main_wl.run(args.steps, args.warmup)
+    n, c, h, w, k = main_wl.shape
+    dominant = "warp_backward" if r["bwd_ms"] >= r["fwd_ms"] else "warp_forward"
+    dom_ms = r["bwd_ms"] if dominant == "warp_backward" else r["fwd_ms"]
+    dom_bytes = main_wl.bwd_bytes if dominant == "warp_backward" else main_wl.fwd_bytes
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    wl_name = main_wl.name()
+    traffic = load_traffic(dominant, wl_name)
+    main_wl.free()
+
+    variants = []
+    if not args.no_variants:
+        todo = [(args.config, "f16" if args.dtype == "f32" else "f32")]
+        if args.config == 2:
+            todo += [(3, "f32"), (3, "f16")]
+        for idx, dt in todo:
+            wl = Workload(idx, dt, dev)
+            vr = wl.run(max(5, args.steps // 3), 2)
+            variants.append({"workload": wl.name(), "fwd_bwd_mpix_s": round(vr["mpix_s"], 1),
+                             "fwd_mpix_s": round(vr["fwd_mpix_s"], 1),
+                             "fwd_ms": round(vr["fwd_ms"], 4), "bwd_ms": round(vr["bwd_ms"], 4),
+                             "fwd_hbm_frac": round(vr["fwd_gbs"] / HBM_PEAK_GBS, 4),
+                             "bwd_hbm_frac": round(vr["bwd_gbs"] / HBM_PEAK_GBS, 4)})
+            wl.free()
+
+    ceiling = copy_ceiling(dev)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.config)
+
+    rec = {
+        "metric": "Mpix/s warp fwd+bwd (output pixels per second)",
+        "value": round(r["mpix_s"], 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl_name, "frames": n, "channels": c, "height": h, "width": w,
+                   "phases": k, "storage": args.dtype, "motion": "fp32"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "breakdown": {"fwd_ms": round(r["fwd_ms"], 4), "bwd_ms": round(r["bwd_ms"], 4),
+                      "fwd_mpix_s": round(r["fwd_mpix_s"], 1),
+                      "fwd_gbs": round(r["fwd_gbs"], 1), "bwd_gbs": round(r["bwd_gbs"], 1),
+                      "fwd_alg_bytes": main_wl.fwd_bytes, "bwd_alg_bytes": main_wl.bwd_bytes,
+                      "copy_ceiling_gbs": round(ceiling, 1)},
+        "variants": variants,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

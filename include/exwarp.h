@@ -1,0 +1,155 @@
+/*
+ * exwarp — motion-vector frame warping on AMD Instinct MI355X (gfx950).
+ *
+ * The fast branch of ExWarp predicts the frames shown between two rendered
+ * frames by warping the last rendered frame F_t (paper §II-B: warping maps
+ * every location of one image to a location in another) with its per-pixel
+ * motion vectors (§III-D), for the display instants t + i/4, i = 1..3
+ * (§IV-B, problem formulation: P_i is made from F_t alone, without F_t+1).
+ * Warped pixels whose source lies outside the frame are marked invalid
+ * (§III-B). The adjoint gives the gradients needed to train a learned
+ * extrapolator through the warp.
+ *
+ * Definition of one output pixel (x, y) of frame n at phase s:
+ *   (u, v) = mv[n, 0:2, y, x]           motion of the content over one
+ *                                       rendered-frame interval, in pixels,
+ *                                       +x right, +y down
+ *   d = (s*u, s*v) rounded to float32   displacement
+ *   (sx, sy) = (x - d.x, y - d.y)       sample point in F_n, pixel-index units
+ *   valid  <=>  0 <= sx <= W-1  and  0 <= sy <= H-1   (NaN/Inf -> invalid)
+ *   out[c] = bilinear sample of F_n[c] at (sx, sy), taps (x0, y0)..(x0+1, y0+1),
+ *            x0 = floor(sx), second index clamped to W-1 / H-1 (its weight is 0
+ *            there); out = 0 in every channel and mask = 0 where invalid.
+ * Coordinates, weights and blending are float32; frames may be stored as
+ * float32, float16 or bfloat16 (results are rounded to nearest-even into the
+ * storage type); motion vectors are always float32.
+ *
+ * Layouts (all dense, row-major, no padding):
+ *   src       [N, C, H, W]     storage dtype          (the frames F_t)
+ *   mv        [N, 2, H, W]     float32                (u plane, then v plane)
+ *   out       [N, K, C, H, W]  storage dtype          (P for each phase)
+ *   mask      [N, K, H, W]     uint8, 1 = valid
+ *   invalid_count [N, K]       uint32
+ *   grad_out  [N, K, C, H, W]  storage dtype
+ *   grad_src  [N, C, H, W]     storage dtype
+ *   grad_mv   [N, 2, H, W]     float32
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device memory on the current device; `phases`
+ *     is a HOST array of K floats read before the call returns.
+ *   - The caller owns all memory. The library allocates nothing and keeps no
+ *     pointer after a call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without synchronising. Faults inside kernels
+ *     surface at the caller's next synchronisation.
+ *   - Outputs are overwritten, never accumulated into.
+ *   - Arguments are fully validated before any HIP call; a rejected call
+ *     enqueues nothing and returns EXW_ERROR_INVALID_VALUE or
+ *     EXW_ERROR_UNSUPPORTED with a message in exw_last_error().
+ *   - Outputs may not overlap inputs or each other (no in-place warping).
+ *   - A batch with N = 0, H = 0 or W = 0 is valid and does no work beyond
+ *     zeroing invalid_count (if given).
+ *   - Thread-safe: the only state is the calling thread's last error string.
+ */
+#ifndef EXWARP_H
+#define EXWARP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXW_ABI_VERSION 1
+#define EXW_MAX_PHASES 4   /* K, phases fused into one launch */
+#define EXW_MAX_CHANNELS 64
+
+typedef enum exw_dtype {
+    EXW_F32 = 0,   /* IEEE binary32 */
+    EXW_F16 = 1,   /* IEEE binary16 */
+    EXW_BF16 = 2   /* bfloat16: the upper 16 bits of a binary32 */
+} exw_dtype;
+
+typedef enum exw_status {
+    EXW_SUCCESS = 0,
+    EXW_ERROR_INVALID_VALUE = 1, /* bad pointer, size, alignment, overlap, phase */
+    EXW_ERROR_UNSUPPORTED = 2,   /* valid request beyond what this library handles */
+    EXW_ERROR_LAUNCH = 3         /* a HIP call or kernel launch failed */
+} exw_status;
+
+/* Returns EXW_ABI_VERSION of the built library. */
+int exw_abi_version(void);
+
+/* Static, never-NULL name of a status code ("EXW_SUCCESS", ...). */
+const char *exw_status_string(int status);
+
+/* Detail of the calling thread's last failed call ("" after a success).
+ * Valid until the thread's next exwarp call. */
+const char *exw_last_error(void);
+
+/*
+ * Forward warp of N frames at K phases in one launch (paper §IV-B: the three
+ * predicted frames P_1..P_3 at t + 1/4, 2/4, 3/4 come from the same F_t, so
+ * the motion field and source frame are read once for all K).
+ *   src, mv, out: required device pointers (layouts above).
+ *   phases: host array of k finite floats (s = i/4 in the method; any finite
+ *           value is accepted, 0 gives the identity).
+ *   k: 1..EXW_MAX_PHASES.   n >= 0, 1 <= c <= EXW_MAX_CHANNELS, h, w >= 0,
+ *   h*w < 2^31.
+ *   mask: optional [N,K,H,W] uint8 output, or NULL.
+ *   invalid_count: optional [N,K] uint32 output (number of invalid pixels
+ *           per frame and phase, paper §III-C holes statistic restricted to
+ *           out-of-frame sources), or NULL.
+ */
+exw_status exw_warp_forward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                    int32_t h, int32_t w, const float *mv, const float *phases,
+                                    int32_t k, void *out, uint8_t *mask,
+                                    uint32_t *invalid_count, void *stream);
+
+/* One frame [C,H,W] at one phase; same as the batched call with N = K = 1
+ * (out [C,H,W], mask [H,W] or NULL). */
+exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,
+                            const float *mv, float phase, void *out, uint8_t *mask,
+                            void *stream);
+
+/* Bytes of float32 workspace the backward call needs: 0 for EXW_F32,
+ * 4*N*C*H*W for EXW_F16/EXW_BF16 when grad_src is requested. */
+size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                                         int32_t w);
+
+/*
+ * Adjoint of exw_warp_forward_batched: given grad_out = dL/d out, writes
+ *   grad_src = dL/d src  = sum over k of the transpose of the bilinear gather
+ *              (each valid output pixel sends weight * grad_out to its four
+ *              taps), accumulated in float32 and rounded once into dtype;
+ *   grad_mv  = dL/d mv   = -s * sum_c grad_out[c] * d out[c]/d(sx, sy),
+ *              summed over k, 0 at invalid pixels; at a floor kink the
+ *              derivative is the one-sided one of the cell the pixel samples.
+ * The derivative treats the displacement as s*u exactly (its float32
+ * rounding is not differentiated). The phase and the mask get no gradient.
+ *   src: required if grad_mv is requested, else may be NULL.
+ *   grad_src: optional (NULL = not computed). grad_mv: optional.
+ *   workspace: device memory of at least
+ *           exw_warp_backward_workspace_bytes(...) bytes, 4-byte aligned
+ *           (may be NULL when that is 0). Its contents are scratch.
+ * Image gradients are accumulated with float32 atomics, so their summation
+ * order, and hence their last bits, can differ from run to run.
+ */
+exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                     int32_t h, int32_t w, const float *mv, const float *phases,
+                                     int32_t k, const void *grad_out, void *grad_src,
+                                     float *grad_mv, void *workspace, size_t workspace_bytes,
+                                     void *stream);
+
+/* One frame at one phase; same as the batched call with N = K = 1. */
+exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,
+                             const float *mv, float phase, const void *grad_out, void *grad_src,
+                             float *grad_mv, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXWARP_H */

@@ -1,0 +1,106 @@
+"""exwarp: motion-vector frame warping for ExWarp's fast branch on MI355X.
+
+The last rendered frame is warped with its per-pixel motion vectors, scaled
+by the extrapolation phase, to predict the frames shown between rendered
+frames (paper §II-B, §III-D, §IV-B). The work runs in hand-written HIP
+kernels behind the C-ABI of ``libexwarp.so`` (``include/exwarp.h``); this
+package marshals torch tensors to that ABI:
+
+* ``binding.exw_*``: the C-ABI entry points under the same names.
+* ``warp``: allocate outputs and run the batched forward warp.
+* ``WarpFunction`` / ``warp_differentiable``: autograd over the hand-written
+  adjoint (gradients for the frames and the motion vectors).
+"""
+
+from __future__ import annotations
+
+from typing import Sequence
+
+import torch
+
+from ._capi import ExwError, lib  # noqa: F401  (lib() raises if the library is missing)
+from .binding import (  # noqa: F401
+    exw_warp_backward,
+    exw_warp_backward_batched,
+    exw_warp_backward_workspace_bytes,
+    exw_warp_forward,
+    exw_warp_forward_batched,
+)
+
+# Fail at import, not at first use, when the native library is absent.
+lib()
+
+
+def warp(src: torch.Tensor, mv: torch.Tensor, phases: Sequence[float] = (1.0,), *,
+         return_mask: bool = False, return_count: bool = False):
+    """Warp ``src`` [N,C,H,W] by ``mv`` [N,2,H,W] at each phase.
+
+    Returns ``out`` [N,K,C,H,W] (dtype of ``src``), plus ``mask`` [N,K,H,W]
+    uint8 and/or ``invalid_count`` [N,K] int32 when asked for.
+    """
+    src = src.contiguous()
+    mv = mv.contiguous()
+    n, c, h, w = src.shape
+    k = len(phases)
+    out = torch.empty((n, k, c, h, w), dtype=src.dtype, device=src.device)
+    mask = torch.empty((n, k, h, w), dtype=torch.uint8, device=src.device) if return_mask else None
+    cnt = torch.empty((n, k), dtype=torch.int32, device=src.device) if return_count else None
+    exw_warp_forward_batched(src, mv, phases, out, mask, cnt)
+    res = [out]
+    if return_mask:
+        res.append(mask)
+    if return_count:
+        res.append(cnt)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def warp_backward(src, mv, phases, grad_out, *, need_src: bool = True, need_mv: bool = True):
+    """Gradients of the batched warp: ``(grad_src or None, grad_mv or None)``."""
+    grad_out = grad_out.contiguous()
+    n, k, c, h, w = grad_out.shape
+    dev = grad_out.device
+    gs = torch.empty((n, c, h, w), dtype=grad_out.dtype, device=dev) if need_src else None
+    gm = torch.empty((n, 2, h, w), dtype=torch.float32, device=dev) if need_mv else None
+    ws = None
+    if need_src:
+        nbytes = exw_warp_backward_workspace_bytes(grad_out.dtype, n, c, h, w)
+        if nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    exw_warp_backward_batched(src.contiguous() if need_mv else None, mv.contiguous(), phases,
+                              grad_out, gs, gm, ws)
+    return gs, gm
+
+
+class WarpFunction(torch.autograd.Function):
+    """Differentiable warp: ``out = WarpFunction.apply(src, mv, phases)``.
+
+    Gradients flow to ``src`` (the frames) and ``mv`` (the motion vectors);
+    the phases and the validity mask are not differentiated.
+    """
+
+    @staticmethod
+    def forward(ctx, src, mv, phases):
+        phases = tuple(float(s) for s in phases)
+        out = warp(src, mv, phases)
+        ctx.phases = phases
+        ctx.save_for_backward(src, mv)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        src, mv = ctx.saved_tensors
+        need_src, need_mv = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_src or need_mv):
+            return None, None, None
+        gs, gm = warp_backward(src, mv, ctx.phases, grad_out.to(src.dtype),
+                               need_src=need_src, need_mv=need_mv)
+        return gs, gm, None
+
+
+def warp_differentiable(src, mv, phases=(1.0,)):
+    return WarpFunction.apply(src, mv, tuple(phases))
+
+
+__all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differentiable",
+           "exw_warp_forward", "exw_warp_forward_batched", "exw_warp_backward",
+           "exw_warp_backward_batched", "exw_warp_backward_workspace_bytes"]

@@ -1,0 +1,158 @@
+"""Thin Python binding of libexwarp: the C-ABI entry points under the same
+names, taking torch tensors (device memory) and the current HIP stream.
+
+Each function checks that tensor shapes, dtypes, devices and contiguity match
+the layouts of include/exwarp.h (the library trusts the sizes it is given),
+then passes raw pointers. All arithmetic happens in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _capi
+from ._capi import EXW_BF16, EXW_F16, EXW_F32, EXW_MAX_PHASES, ExwError, check, lib
+
+DTYPES = {torch.float32: EXW_F32, torch.float16: EXW_F16, torch.bfloat16: EXW_BF16}
+
+
+def exw_dtype(t: torch.dtype) -> int:
+    try:
+        return DTYPES[t]
+    except KeyError:
+        raise TypeError(f"unsupported frame dtype {t}; use float32, float16 or bfloat16") from None
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, name: str, device: torch.device) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _expect(t: Optional[torch.Tensor], name: str, shape: Sequence[int], dtype: torch.dtype,
+            device: torch.device) -> None:
+    if t is None:
+        return
+    _dev(t, name, device)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+
+
+def _phases(phases) -> tuple:
+    ph = [float(s) for s in phases]
+    if not 1 <= len(ph) <= EXW_MAX_PHASES:
+        raise ValueError(f"need 1..{EXW_MAX_PHASES} phases, got {len(ph)}")
+    arr = (ctypes.c_float * len(ph))(*ph)
+    return arr, len(ph)
+
+
+def _stream(device: torch.device, stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def exw_warp_forward_batched(src: torch.Tensor, mv: torch.Tensor, phases, out: torch.Tensor,
+                             mask: Optional[torch.Tensor] = None,
+                             invalid_count: Optional[torch.Tensor] = None, stream=None) -> None:
+    """src [N,C,H,W], mv [N,2,H,W] f32, out [N,K,C,H,W], mask [N,K,H,W] u8,
+    invalid_count [N,K] int32 (read as uint32)."""
+    dev = src.device
+    _dev(src, "src", dev)
+    n, c, h, w = src.shape
+    arr, k = _phases(phases)
+    _expect(mv, "mv", (n, 2, h, w), torch.float32, dev)
+    _expect(out, "out", (n, k, c, h, w), src.dtype, dev)
+    _expect(mask, "mask", (n, k, h, w), torch.uint8, dev)
+    _expect(invalid_count, "invalid_count", (n, k), torch.int32, dev)
+    st = lib().exw_warp_forward_batched(_ptr(src), exw_dtype(src.dtype), n, c, h, w, _ptr(mv),
+                                        arr, k, _ptr(out), _ptr(mask), _ptr(invalid_count),
+                                        _stream(dev, stream))
+    check(st, "exw_warp_forward_batched")
+
+
+def exw_warp_forward(src: torch.Tensor, mv: torch.Tensor, phase: float, out: torch.Tensor,
+                     mask: Optional[torch.Tensor] = None, stream=None) -> None:
+    """One frame: src [C,H,W], mv [2,H,W] f32, out [C,H,W], mask [H,W] u8."""
+    dev = src.device
+    _dev(src, "src", dev)
+    c, h, w = src.shape
+    _expect(mv, "mv", (2, h, w), torch.float32, dev)
+    _expect(out, "out", (c, h, w), src.dtype, dev)
+    _expect(mask, "mask", (h, w), torch.uint8, dev)
+    st = lib().exw_warp_forward(_ptr(src), exw_dtype(src.dtype), c, h, w, _ptr(mv),
+                                ctypes.c_float(phase), _ptr(out), _ptr(mask),
+                                _stream(dev, stream))
+    check(st, "exw_warp_forward")
+
+
+def exw_warp_backward_workspace_bytes(dtype: torch.dtype, n: int, c: int, h: int, w: int) -> int:
+    return int(lib().exw_warp_backward_workspace_bytes(exw_dtype(dtype), n, c, h, w))
+
+
+def exw_warp_backward_batched(src: Optional[torch.Tensor], mv: torch.Tensor, phases,
+                              grad_out: torch.Tensor, grad_src: Optional[torch.Tensor] = None,
+                              grad_mv: Optional[torch.Tensor] = None,
+                              workspace: Optional[torch.Tensor] = None, stream=None) -> None:
+    """grad_out [N,K,C,H,W] -> grad_src [N,C,H,W] (dtype of grad_out) and/or
+    grad_mv [N,2,H,W] f32. ``workspace``: a byte tensor of at least
+    ``exw_warp_backward_workspace_bytes`` bytes (needed for f16/bf16 grad_src)."""
+    dev = grad_out.device
+    _dev(grad_out, "grad_out", dev)
+    n, k, c, h, w = grad_out.shape
+    arr, k2 = _phases(phases)
+    if k2 != k:
+        raise ValueError(f"grad_out has {k} phases, got {k2} phase values")
+    dt = grad_out.dtype
+    _expect(src, "src", (n, c, h, w), dt, dev)
+    _expect(mv, "mv", (n, 2, h, w), torch.float32, dev)
+    _expect(grad_src, "grad_src", (n, c, h, w), dt, dev)
+    _expect(grad_mv, "grad_mv", (n, 2, h, w), torch.float32, dev)
+    ws_bytes = 0
+    if workspace is not None:
+        _dev(workspace, "workspace", dev)
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib().exw_warp_backward_batched(_ptr(src), exw_dtype(dt), n, c, h, w, _ptr(mv), arr, k,
+                                         _ptr(grad_out), _ptr(grad_src), _ptr(grad_mv),
+                                         _ptr(workspace), ws_bytes, _stream(dev, stream))
+    check(st, "exw_warp_backward_batched")
+
+
+def exw_warp_backward(src: Optional[torch.Tensor], mv: torch.Tensor, phase: float,
+                      grad_out: torch.Tensor, grad_src: Optional[torch.Tensor] = None,
+                      grad_mv: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None, stream=None) -> None:
+    """One frame: grad_out [C,H,W] -> grad_src [C,H,W], grad_mv [2,H,W]."""
+    dev = grad_out.device
+    _dev(grad_out, "grad_out", dev)
+    c, h, w = grad_out.shape
+    dt = grad_out.dtype
+    _expect(src, "src", (c, h, w), dt, dev)
+    _expect(mv, "mv", (2, h, w), torch.float32, dev)
+    _expect(grad_src, "grad_src", (c, h, w), dt, dev)
+    _expect(grad_mv, "grad_mv", (2, h, w), torch.float32, dev)
+    ws_bytes = 0
+    if workspace is not None:
+        _dev(workspace, "workspace", dev)
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib().exw_warp_backward(_ptr(src), exw_dtype(dt), c, h, w, _ptr(mv),
+                                 ctypes.c_float(phase), _ptr(grad_out), _ptr(grad_src),
+                                 _ptr(grad_mv), _ptr(workspace), ws_bytes, _stream(dev, stream))
+    check(st, "exw_warp_backward")
+
+
+__all__ = ["ExwError", "exw_dtype", "exw_warp_forward_batched", "exw_warp_forward",
+           "exw_warp_backward_workspace_bytes", "exw_warp_backward_batched", "exw_warp_backward",
+           "_capi"]

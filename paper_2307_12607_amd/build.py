@@ -1,0 +1,48 @@
+"""Build ``libexwarp.so`` (the C-ABI library and its gfx950 kernels) with hipcc, in-tree."""
+
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libexwarp.so")
+SOURCES = [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "warp_kernels.hip")]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # The displacement s*u must be rounded once; FMAs are written explicitly.
+    "-ffp-contract=off",
+    # Keep float32 denormals: tiny displacements must not flush to zero.
+    "-fno-gpu-flush-denormals-to-zero",
+    # Hardware float32 atomics on coarse-grained device memory.
+    "-munsafe-fp-atomics",
+    # No packed-FP32 instructions (a hipcc flag; the host pass ignores it).
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall",
+    "-Wno-unused-command-line-argument",
+    "-Wno-pass-failed",
+]
+
+
+def build(verbose: bool = False) -> str:
+    cmd = [HIPCC, *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *SOURCES, "-o", LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,256 @@
+// C-ABI of libexwarp: argument validation, then dispatch to the HIP kernels.
+// Every check runs before the first HIP call, so a rejected call touches
+// neither the device nor the stream. See include/exwarp.h for the contract.
+#include "exwarp.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+exw_status fail(exw_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+exw_status succeed() {
+    g_last_error.clear();
+    return EXW_SUCCESS;
+}
+
+size_t dtype_size(int dtype) {
+    switch (dtype) {
+    case EXW_F32: return 4;
+    case EXW_F16: return 2;
+    case EXW_BF16: return 2;
+    default: return 0;
+    }
+}
+
+struct Span {
+    const char *name;
+    uintptr_t lo, hi;  // [lo, hi)
+};
+
+Span span(const char *name, const void *p, uint64_t bytes) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return Span{name, lo, p ? lo + bytes : lo};
+}
+
+bool overlaps(const Span &a, const Span &b) {
+    return a.lo != a.hi && b.lo != b.hi && a.lo < b.hi && b.lo < a.hi;
+}
+
+// Largest element count of any buffer the library indexes: keeps every
+// 64-bit offset far from overflow.
+constexpr uint64_t kMaxElems = uint64_t(1) << 40;
+
+struct Checked {
+    exw::WarpShape shape;
+    uint64_t hw = 0, img_elems = 0, out_elems = 0, mv_elems = 0;
+    size_t esize = 0;
+    bool empty = false;
+};
+
+exw_status check_common(exw_dtype dtype, int32_t n, int32_t c, int32_t h, int32_t w,
+                        const float *phases, int32_t k, Checked *ck) {
+    ck->esize = dtype_size(dtype);
+    if (ck->esize == 0) return fail(EXW_ERROR_INVALID_VALUE, "unknown dtype %d", int(dtype));
+    if (n < 0 || h < 0 || w < 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "negative size (n=%d, h=%d, w=%d)", n, h, w);
+    if (c < 1) return fail(EXW_ERROR_INVALID_VALUE, "channel count %d < 1", c);
+    if (c > EXW_MAX_CHANNELS)
+        return fail(EXW_ERROR_UNSUPPORTED, "channel count %d > %d", c, EXW_MAX_CHANNELS);
+    if (k < 1) return fail(EXW_ERROR_INVALID_VALUE, "phase count %d < 1", k);
+    if (k > EXW_MAX_PHASES)
+        return fail(EXW_ERROR_UNSUPPORTED, "phase count %d > %d", k, EXW_MAX_PHASES);
+    if (!phases) return fail(EXW_ERROR_INVALID_VALUE, "phases is NULL");
+    for (int j = 0; j < k; ++j)
+        if (!std::isfinite(phases[j]))
+            return fail(EXW_ERROR_INVALID_VALUE, "phase %d is not finite", j);
+    // Frame coordinates must be exact in float32 and a plane index must fit int32.
+    if (h >= (1 << 24) || w >= (1 << 24))
+        return fail(EXW_ERROR_UNSUPPORTED, "frame side >= 2^24 (h=%d, w=%d)", h, w);
+    ck->hw = uint64_t(h) * uint64_t(w);
+    if (ck->hw >= (uint64_t(1) << 31))
+        return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu >= 2^31", (unsigned long long)ck->hw);
+    ck->img_elems = uint64_t(n) * uint64_t(c) * ck->hw;
+    ck->out_elems = ck->img_elems * uint64_t(k);
+    ck->mv_elems = uint64_t(n) * 2u * ck->hw;
+    if (ck->out_elems > kMaxElems)
+        return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu output elements)",
+                    (unsigned long long)ck->out_elems);
+    // One workgroup per 64x4 tile must fit a 1-D grid.
+    const uint64_t tiles = uint64_t(n) * ((uint64_t(w) + 63) / 64) * ((uint64_t(h) + 3) / 4);
+    if (tiles >= (uint64_t(1) << 31))
+        return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu tiles)", (unsigned long long)tiles);
+    ck->empty = (n == 0 || h == 0 || w == 0);
+    ck->shape.n = n;
+    ck->shape.c = c;
+    ck->shape.h = h;
+    ck->shape.w = w;
+    ck->shape.k = k;
+    for (int j = 0; j < 4; ++j) ck->shape.phases[j] = j < k ? phases[j] : 0.0f;
+    return EXW_SUCCESS;
+}
+
+exw_status check_ptr(const char *name, const void *p, size_t align, bool required) {
+    if (!p) {
+        if (required) return fail(EXW_ERROR_INVALID_VALUE, "%s is NULL", name);
+        return EXW_SUCCESS;
+    }
+    if (reinterpret_cast<uintptr_t>(p) % align != 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "%s is not %zu-byte aligned", name, align);
+    return EXW_SUCCESS;
+}
+
+exw_status check_disjoint(const Span *outs, int n_out, const Span *ins, int n_in) {
+    for (int i = 0; i < n_out; ++i) {
+        for (int j = 0; j < n_in; ++j)
+            if (overlaps(outs[i], ins[j]))
+                return fail(EXW_ERROR_INVALID_VALUE, "%s overlaps input %s", outs[i].name,
+                            ins[j].name);
+        for (int j = i + 1; j < n_out; ++j)
+            if (overlaps(outs[i], outs[j]))
+                return fail(EXW_ERROR_INVALID_VALUE, "%s overlaps output %s", outs[i].name,
+                            outs[j].name);
+    }
+    return EXW_SUCCESS;
+}
+
+exw_status launched(hipError_t e, const char *what) {
+    if (e != hipSuccess)
+        return fail(EXW_ERROR_LAUNCH, "%s: %s", what, hipGetErrorString(e));
+    return succeed();
+}
+
+#define EXW_TRY(expr)                                  \
+    do {                                               \
+        exw_status st_ = (expr);                       \
+        if (st_ != EXW_SUCCESS) return st_;            \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int exw_abi_version(void) { return EXW_ABI_VERSION; }
+
+const char *exw_status_string(int status) {
+    switch (status) {
+    case EXW_SUCCESS: return "EXW_SUCCESS";
+    case EXW_ERROR_INVALID_VALUE: return "EXW_ERROR_INVALID_VALUE";
+    case EXW_ERROR_UNSUPPORTED: return "EXW_ERROR_UNSUPPORTED";
+    case EXW_ERROR_LAUNCH: return "EXW_ERROR_LAUNCH";
+    default: return "EXW_UNKNOWN_STATUS";
+    }
+}
+
+const char *exw_last_error(void) { return g_last_error.c_str(); }
+
+exw_status exw_warp_forward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                    int32_t h, int32_t w, const float *mv, const float *phases,
+                                    int32_t k, void *out, uint8_t *mask,
+                                    uint32_t *invalid_count, void *stream) {
+    Checked ck;
+    EXW_TRY(check_common(dtype, n, c, h, w, phases, k, &ck));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t nk = uint64_t(n) * uint64_t(k);
+    EXW_TRY(check_ptr("invalid_count", invalid_count, 4, false));
+    if (ck.empty) {
+        if (invalid_count && nk > 0)
+            return launched(exw::launch_zero_u32(invalid_count, int64_t(nk), st), "zero count");
+        return succeed();
+    }
+    EXW_TRY(check_ptr("src", src, ck.esize, true));
+    EXW_TRY(check_ptr("mv", mv, 4, true));
+    EXW_TRY(check_ptr("out", out, ck.esize, true));
+    EXW_TRY(check_ptr("mask", mask, 1, false));
+    const Span ins[] = {span("src", src, ck.img_elems * ck.esize),
+                        span("mv", mv, ck.mv_elems * 4)};
+    const Span outs[] = {span("out", out, ck.out_elems * ck.esize),
+                         span("mask", mask, nk * ck.hw),
+                         span("invalid_count", invalid_count, nk * 4)};
+    EXW_TRY(check_disjoint(outs, 3, ins, 2));
+    return launched(exw::launch_forward(dtype, src, mv, ck.shape, out, mask, invalid_count, st),
+                    "warp forward launch");
+}
+
+exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,
+                            const float *mv, float phase, void *out, uint8_t *mask,
+                            void *stream) {
+    return exw_warp_forward_batched(src, dtype, 1, c, h, w, mv, &phase, 1, out, mask, nullptr,
+                                    stream);
+}
+
+size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                                         int32_t w) {
+    if (dtype != EXW_F16 && dtype != EXW_BF16) return 0;
+    if (n <= 0 || c <= 0 || h <= 0 || w <= 0) return 0;
+    return size_t(n) * size_t(c) * size_t(h) * size_t(w) * sizeof(float);
+}
+
+exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                     int32_t h, int32_t w, const float *mv, const float *phases,
+                                     int32_t k, const void *grad_out, void *grad_src,
+                                     float *grad_mv, void *workspace, size_t workspace_bytes,
+                                     void *stream) {
+    Checked ck;
+    EXW_TRY(check_common(dtype, n, c, h, w, phases, k, &ck));
+    if (ck.empty || (!grad_src && !grad_mv)) return succeed();
+    EXW_TRY(check_ptr("src", src, ck.esize, grad_mv != nullptr));
+    EXW_TRY(check_ptr("mv", mv, 4, true));
+    EXW_TRY(check_ptr("grad_out", grad_out, ck.esize, true));
+    EXW_TRY(check_ptr("grad_src", grad_src, ck.esize, false));
+    EXW_TRY(check_ptr("grad_mv", grad_mv, 4, false));
+    const bool needs_ws = grad_src && dtype != EXW_F32;
+    const uint64_t ws_need = needs_ws ? ck.img_elems * 4 : 0;
+    if (needs_ws) {
+        EXW_TRY(check_ptr("workspace", workspace, 4, true));
+        if (workspace_bytes < ws_need)
+            return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %llu",
+                        workspace_bytes, (unsigned long long)ws_need);
+    }
+    const Span ins[] = {span("src", src, ck.img_elems * ck.esize),
+                        span("mv", mv, ck.mv_elems * 4),
+                        span("grad_out", grad_out, ck.out_elems * ck.esize)};
+    const Span outs[] = {span("grad_src", grad_src, ck.img_elems * ck.esize),
+                         span("grad_mv", grad_mv, ck.mv_elems * 4),
+                         span("workspace", needs_ws ? workspace : nullptr, ws_need)};
+    EXW_TRY(check_disjoint(outs, 3, ins, 3));
+    float *accum = nullptr;
+    void *cast_to = nullptr;
+    if (grad_src) {
+        if (dtype == EXW_F32) {
+            accum = static_cast<float *>(grad_src);
+        } else {
+            accum = static_cast<float *>(workspace);
+            cast_to = grad_src;
+        }
+    }
+    return launched(exw::launch_backward(dtype, grad_mv ? src : nullptr, mv, ck.shape, grad_out,
+                                         accum, cast_to, grad_mv,
+                                         static_cast<hipStream_t>(stream)),
+                    "warp backward launch");
+}
+
+exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,
+                             const float *mv, float phase, const void *grad_out, void *grad_src,
+                             float *grad_mv, void *workspace, size_t workspace_bytes,
+                             void *stream) {
+    return exw_warp_backward_batched(src, dtype, 1, c, h, w, mv, &phase, 1, grad_out, grad_src,
+                                     grad_mv, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+"""The C-ABI library without a GPU: it loads, exports what the header declares,
+and rejects bad arguments before any HIP call."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2307_12607_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "exwarp.h")
+
+F = ctypes.c_float
+FAKE = 0x7f0000000000  # aligned fake device address; never dereferenced on the CPU
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(exw_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    assert names == sorted(_capi.SIGNATURES), names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _capi.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _capi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (exw_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_abi_version_and_status_strings():
+    L = _capi.lib()
+    assert L.exw_abi_version() == 1
+    assert _capi.status_string(0) == "EXW_SUCCESS"
+    assert _capi.status_string(1) == "EXW_ERROR_INVALID_VALUE"
+    assert _capi.status_string(2) == "EXW_ERROR_UNSUPPORTED"
+    assert _capi.status_string(3) == "EXW_ERROR_LAUNCH"
+    assert _capi.status_string(99) == "EXW_UNKNOWN_STATUS"
+
+
+def _phases(*vals):
+    return (F * len(vals))(*vals)
+
+
+def fwd(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=None, k=1,
+        out=FAKE + (2 << 30), mask=None, count=None):
+    if phases is None:
+        phases = _phases(1.0)
+    return _capi.lib().exw_warp_forward_batched(src, dtype, n, c, h, w, mv, phases, k, out, mask,
+                                                count, None)
+
+
+def bwd(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=None, k=1,
+        gout=FAKE + (2 << 30), gsrc=FAKE + (3 << 30), gmv=FAKE + (4 << 30), ws=None, ws_bytes=0):
+    if phases is None:
+        phases = _phases(1.0)
+    return _capi.lib().exw_warp_backward_batched(src, dtype, n, c, h, w, mv, phases, k, gout,
+                                                 gsrc, gmv, ws, ws_bytes, None)
+
+
+INVALID, UNSUPPORTED = _capi.EXW_ERROR_INVALID_VALUE, _capi.EXW_ERROR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(dtype=7), INVALID, "dtype"),
+    (dict(n=-1), INVALID, "negative"),
+    (dict(h=-2), INVALID, "negative"),
+    (dict(c=0), INVALID, "channel"),
+    (dict(c=65), UNSUPPORTED, "channel"),
+    (dict(k=0), INVALID, "phase count"),
+    (dict(k=5, phases=(F * 5)(1, 1, 1, 1, 1)), UNSUPPORTED, "phase count"),
+    (dict(phases=_phases(float("nan"))), INVALID, "not finite"),
+    (dict(phases=_phases(float("inf"))), INVALID, "not finite"),
+    (dict(src=None), INVALID, "src is NULL"),
+    (dict(mv=None), INVALID, "mv is NULL"),
+    (dict(out=None), INVALID, "out is NULL"),
+    (dict(src=FAKE + 2), INVALID, "aligned"),
+    (dict(mask=FAKE + 64), INVALID, "mask overlaps input src"),
+    (dict(mv=FAKE + 1 + (1 << 30)), INVALID, "aligned"),
+    (dict(out=FAKE + 100), INVALID, "overlaps input src"),
+    (dict(mask=FAKE + (2 << 30) + 16), INVALID, "out overlaps output mask"),
+    (dict(count=FAKE + (1 << 30) + 8), INVALID, "overlaps input mv"),
+    (dict(count=FAKE + 2 + (5 << 30)), INVALID, "aligned"),
+    (dict(h=1 << 24, w=1), UNSUPPORTED, "2^24"),
+    (dict(h=1 << 16, w=1 << 16), UNSUPPORTED, "2^31"),
+    (dict(n=1 << 20, c=64, h=4096, w=4096, k=1), UNSUPPORTED, "too large"),
+])
+def test_forward_rejects(kwargs, status, needle):
+    st = fwd(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(dtype=3), INVALID, "dtype"),
+    (dict(gout=None), INVALID, "grad_out is NULL"),
+    (dict(src=None), INVALID, "src is NULL"),
+    (dict(mv=None), INVALID, "mv is NULL"),
+    (dict(dtype=1, ws=None), INVALID, "workspace is NULL"),
+    (dict(dtype=2, ws=FAKE + (6 << 30), ws_bytes=16), INVALID, "needs"),
+    (dict(gsrc=FAKE + (2 << 30)), INVALID, "grad_src overlaps input grad_out"),
+    (dict(gmv=FAKE), INVALID, "grad_mv overlaps input src"),
+    (dict(gmv=FAKE + (3 << 30) + 64), INVALID, "grad_src overlaps output grad_mv"),
+    (dict(gsrc=FAKE + 1 + (3 << 30)), INVALID, "aligned"),
+    (dict(k=9, phases=(F * 9)(*[1] * 9)), UNSUPPORTED, "phase count"),
+])
+def test_backward_rejects(kwargs, status, needle):
+    st = bwd(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+def test_empty_batches_and_no_requested_gradient_are_no_ops():
+    # No pointer is needed, and nothing is launched (this host has no GPU).
+    assert fwd(n=0, src=None, mv=None, out=None) == 0
+    assert fwd(h=0, src=None, mv=None, out=None) == 0
+    assert _capi.last_error() == ""
+    assert bwd(n=0, src=None, mv=None, gout=None, gsrc=None, gmv=None) == 0
+    assert bwd(gsrc=None, gmv=None) == 0
+
+
+def test_workspace_size():
+    L = _capi.lib()
+    assert L.exw_warp_backward_workspace_bytes(0, 2, 3, 4, 5) == 0
+    assert L.exw_warp_backward_workspace_bytes(1, 2, 3, 4, 5) == 4 * 2 * 3 * 4 * 5
+    assert L.exw_warp_backward_workspace_bytes(2, 8, 12, 1440, 2560) == 4 * 8 * 12 * 1440 * 2560
+    assert L.exw_warp_backward_workspace_bytes(2, 0, 3, 4, 5) == 0
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    code = ("import paper_2307_12607_amd._capi as c; c.LIB_PATH = '/nonexistent/libexwarp.so'; "
+            "c._lib = None\ntry:\n    c.lib()\nexcept ImportError as e:\n    print('RAISED', e)")
+    res = subprocess.run(["python", "-c", code], capture_output=True, text=True, cwd=ROOT)
+    assert "RAISED" in res.stdout and "build" in res.stdout
+
+
+def test_product_path_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2307_12607_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b|warp_ref|synth", text), f
