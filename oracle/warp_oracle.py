@@ -20,7 +20,9 @@ are:
 * A pixel is valid iff ``0 <= sx <= W-1`` and ``0 <= sy <= H-1`` (a closed
   box: every tap with non-zero weight lies inside the frame). Invalid pixels
   are 0 in every channel, get mask 0, and are counted. NaN/Inf motion is
-  invalid.
+  invalid. The test is evaluated exactly (on the displacement against integer
+  bounds), and the cell as ``x0 = x - ceil(d)`` with fraction ``ceil(d) - d``,
+  so that a displacement far below an ulp of x is not rounded away.
 * The displacement ``s*u`` is rounded once to float32, the precision of the
   motion field, so the validity decision is taken in the same precision on
   every implementation. For phases 0, 1/4, 1/2 and 1 the product is exact, so
@@ -58,18 +60,23 @@ def taps(u: np.ndarray, v: np.ndarray, phase: float, xs: np.ndarray, ys: np.ndar
     Returns ``valid, x0, x1, y0, y1, fx, fy`` (arrays shaped like ``xs``);
     indices and fractions of invalid pixels are set to 0.
     """
-    sx = np.asarray(xs, dtype=np.float64) - displacement(u, phase)
-    sy = np.asarray(ys, dtype=np.float64) - displacement(v, phase)
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    dx = displacement(u, phase)
+    dy = displacement(v, phase)
+    # 0 <= x - d <= W-1, stated on d against integer bounds: exact even where
+    # |d| is below half an ulp of x and forming x - d would round.
     with np.errstate(invalid="ignore"):
-        valid = (sx >= 0.0) & (sx <= w - 1) & (sy >= 0.0) & (sy <= h - 1)
-    sx = np.where(valid, sx, 0.0)
-    sy = np.where(valid, sy, 0.0)
-    x0f = np.floor(sx)
-    y0f = np.floor(sy)
-    fx = sx - x0f
-    fy = sy - y0f
-    x0 = x0f.astype(np.int64)
-    y0 = y0f.astype(np.int64)
+        valid = ((dx <= xs) & (dx >= xs - (w - 1)) & (dy <= ys) & (dy >= ys - (h - 1)))
+    dx = np.where(valid, dx, 0.0)
+    dy = np.where(valid, dy, 0.0)
+    # floor(x - d) = x - ceil(d) for integer x; the fraction is ceil(d) - d.
+    cx = np.ceil(dx)
+    cy = np.ceil(dy)
+    x0 = np.where(valid, xs - cx.astype(np.int64), 0)
+    y0 = np.where(valid, ys - cy.astype(np.int64), 0)
+    fx = cx - dx
+    fy = cy - dy
     x1 = np.minimum(x0 + 1, w - 1)
     y1 = np.minimum(y0 + 1, h - 1)
     return valid, x0, x1, y0, y1, fx, fy

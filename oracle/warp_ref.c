@@ -8,8 +8,8 @@
  * output pixel (x, y) of frame n at phase s samples F_n bilinearly at
  * (x - s*u, y - s*v), (u, v) = mv[n, :, y, x]. The displacement s*u is rounded
  * once to float32 (the motion field's precision); all later steps are float64.
- * Valid iff 0 <= sx <= W-1 and 0 <= sy <= H-1; invalid pixels are 0, mask 0,
- * and are counted. Taps (x0, y0), (x1, y0), (x0, y1), (x1, y1) with
+ * Valid iff 0 <= sx <= W-1 and 0 <= sy <= H-1 (tested exactly on d); invalid
+ * pixels are 0, mask 0, and are counted. Taps (x0, y0), (x1, y0), (x0, y1), (x1, y1) with
  * x0 = floor(sx), x1 = min(x0 + 1, W - 1), weights from the fractions.
  * Backward: the transpose of the gather for the image and the derivative of
  * the blend for the motion (d sx / d u = -s), summed over phases.
@@ -37,17 +37,19 @@ static taps_t make_taps(float u, float v, float s, int64_t x, int64_t y, int64_t
     taps_t t;
     double dx = (double)(float)((double)s * (double)u);
     double dy = (double)(float)((double)s * (double)v);
-    double sx = (double)x - dx;
-    double sy = (double)y - dy;
     memset(&t, 0, sizeof t);
-    t.valid = (sx >= 0.0) && (sx <= (double)(w - 1)) && (sy >= 0.0) && (sy <= (double)(h - 1));
+    /* 0 <= x - d <= W-1 on d against integer bounds (exact even when |d| is
+     * below half an ulp of x). */
+    t.valid = (dx <= (double)x) && (dx >= (double)(x - (w - 1))) && (dy <= (double)y)
+           && (dy >= (double)(y - (h - 1)));
     if (!t.valid)
         return t;
-    double fl_x = floor(sx), fl_y = floor(sy);
-    t.x0 = (int64_t)fl_x;
-    t.y0 = (int64_t)fl_y;
-    t.fx = sx - fl_x;
-    t.fy = sy - fl_y;
+    /* floor(x - d) = x - ceil(d); fraction ceil(d) - d. */
+    double cx = ceil(dx), cy = ceil(dy);
+    t.x0 = x - (int64_t)cx;
+    t.y0 = y - (int64_t)cy;
+    t.fx = cx - dx;
+    t.fy = cy - dy;
     t.x1 = t.x0 + 1 < w ? t.x0 + 1 : w - 1;
     t.y1 = t.y0 + 1 < h ? t.y0 + 1 : h - 1;
     return t;

@@ -132,7 +132,8 @@ def pin_mask_bruteforce(O):
         for b in range(-w - 1, w + 2):
             f = np.float32(b)
             vals += [f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))]
-        vals += [np.float32(0.5), np.float32(-0.25), np.float32(np.nan), np.float32(np.inf)]
+        vals += [np.float32(0.5), np.float32(-0.25), np.float32(np.nan), np.float32(np.inf),
+                 np.float32(1e-40), np.float32(-1e-40), np.float32(-0.0)]
         vals = np.array(vals, dtype=np.float32)
         r = _rng(h * 31 + w)
         for s in (1.0, 0.75, 0.5):
