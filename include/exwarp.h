@@ -113,8 +113,11 @@ exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t
                             const float *mv, float phase, void *out, uint8_t *mask,
                             void *stream);
 
-/* Bytes of float32 workspace the backward call needs: 0 for EXW_F32,
- * 4*N*C*H*W for EXW_F16/EXW_BF16 when grad_src is requested. */
+/* Bytes of device workspace exw_warp_backward_batched needs when grad_src is
+ * requested: per-row-segment tap boxes (16 bytes per 64 output pixels of a
+ * row), 8 bytes per frame, and for EXW_F16/EXW_BF16 a float32 image-gradient
+ * accumulator of 4*N*C*H*W bytes. Returns 0 for an invalid dtype or an empty
+ * batch. */
 size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                                          int32_t w);
 
@@ -130,11 +133,14 @@ size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, 
  * rounding is not differentiated). The phase and the mask get no gradient.
  *   src: required if grad_mv is requested, else may be NULL.
  *   grad_src: optional (NULL = not computed). grad_mv: optional.
- *   workspace: device memory of at least
- *           exw_warp_backward_workspace_bytes(...) bytes, 4-byte aligned
- *           (may be NULL when that is 0). Its contents are scratch.
- * Image gradients are accumulated with float32 atomics, so their summation
- * order, and hence their last bits, can differ from run to run.
+ *   workspace: required when grad_src is requested: device memory of at least
+ *           exw_warp_backward_workspace_bytes(...) bytes, 256-byte aligned;
+ *           its contents are scratch. May be NULL when grad_src is NULL.
+ * The image gradient is formed by gathering, per tile of the image, the
+ * contributions of the output pixels whose taps land there (LDS
+ * accumulation, plain stores); output segments whose taps lie more than 128
+ * px away fall back to float32 atomics. Summation order inside a tile is not
+ * fixed, so the last bits of grad_src can differ from run to run.
  */
 exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
                                      int32_t h, int32_t w, const float *mv, const float *phases,

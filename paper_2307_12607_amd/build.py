@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libexwarp.so")
-SOURCES = [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "warp_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "warp_forward.hip"),
+           os.path.join(CSRC, "warp_backward.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

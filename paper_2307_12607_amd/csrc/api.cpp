@@ -135,6 +135,24 @@ exw_status launched(hipError_t e, const char *what) {
     return succeed();
 }
 
+// Byte offsets of the adjoint's scratch inside the caller's workspace.
+struct WsLayout {
+    size_t boxes, info, accum, total;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+WsLayout workspace_layout(int dtype, int n, int c, int h, int w) {
+    WsLayout l;
+    l.boxes = 0;
+    l.info = align_up(exw::backward_box_bytes(n, h, w));
+    l.accum = align_up(l.info + exw::backward_info_bytes(n));
+    const size_t accum_bytes =
+        dtype == EXW_F32 ? 0 : size_t(n) * size_t(c) * size_t(h) * size_t(w) * sizeof(float);
+    l.total = l.accum + accum_bytes;
+    return l;
+}
+
 #define EXW_TRY(expr)                                  \
     do {                                               \
         exw_status st_ = (expr);                       \
@@ -196,9 +214,8 @@ exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t
 
 size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                                          int32_t w) {
-    if (dtype != EXW_F16 && dtype != EXW_BF16) return 0;
-    if (n <= 0 || c <= 0 || h <= 0 || w <= 0) return 0;
-    return size_t(n) * size_t(c) * size_t(h) * size_t(w) * sizeof(float);
+    if (dtype_size(dtype) == 0 || n <= 0 || c <= 0 || h <= 0 || w <= 0) return 0;
+    return workspace_layout(dtype, n, c, h, w).total;
 }
 
 exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
@@ -214,10 +231,11 @@ exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n
     EXW_TRY(check_ptr("grad_out", grad_out, ck.esize, true));
     EXW_TRY(check_ptr("grad_src", grad_src, ck.esize, false));
     EXW_TRY(check_ptr("grad_mv", grad_mv, 4, false));
-    const bool needs_ws = grad_src && dtype != EXW_F32;
-    const uint64_t ws_need = needs_ws ? ck.img_elems * 4 : 0;
+    const bool needs_ws = grad_src != nullptr;
+    const WsLayout lay = workspace_layout(dtype, n, c, h, w);
+    const uint64_t ws_need = needs_ws ? lay.total : 0;
     if (needs_ws) {
-        EXW_TRY(check_ptr("workspace", workspace, 4, true));
+        EXW_TRY(check_ptr("workspace", workspace, 256, true));
         if (workspace_bytes < ws_need)
             return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %llu",
                         workspace_bytes, (unsigned long long)ws_need);
@@ -229,18 +247,15 @@ exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n
                          span("grad_mv", grad_mv, ck.mv_elems * 4),
                          span("workspace", needs_ws ? workspace : nullptr, ws_need)};
     EXW_TRY(check_disjoint(outs, 3, ins, 3));
-    float *accum = nullptr;
-    void *cast_to = nullptr;
-    if (grad_src) {
-        if (dtype == EXW_F32) {
-            accum = static_cast<float *>(grad_src);
-        } else {
-            accum = static_cast<float *>(workspace);
-            cast_to = grad_src;
-        }
+    exw::BwdWorkspace ws{nullptr, nullptr, nullptr};
+    if (needs_ws) {
+        char *base = static_cast<char *>(workspace);
+        ws.boxes = base + lay.boxes;
+        ws.info = base + lay.info;
+        ws.accum32 = dtype == EXW_F32 ? nullptr : reinterpret_cast<float *>(base + lay.accum);
     }
     return launched(exw::launch_backward(dtype, grad_mv ? src : nullptr, mv, ck.shape, grad_out,
-                                         accum, cast_to, grad_mv,
+                                         grad_src, grad_mv, ws,
                                          static_cast<hipStream_t>(stream)),
                     "warp backward launch");
 }

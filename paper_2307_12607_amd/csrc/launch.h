@@ -1,8 +1,9 @@
 // Internal interface between the C-ABI layer (api.cpp) and the HIP kernels
-// (warp_kernels.hip). Arguments arrive here already validated.
+// (warp_forward.hip, warp_backward.hip). Arguments arrive here validated.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace exw {
@@ -12,16 +13,29 @@ struct WarpShape {
     float phases[4];
 };
 
+struct Phases4 {
+    float s[4];
+};
+
+// Device scratch of the adjoint, carved from the caller's workspace.
+struct BwdWorkspace {
+    void *boxes;     // per row segment: bounding box of its taps
+    void *info;      // per frame: reach of the segments, far flag
+    float *accum32;  // float32 image-gradient accumulator (16-bit storage only)
+};
+
+size_t backward_box_bytes(int n, int h, int w);
+size_t backward_info_bytes(int n);
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t stream);
+
 hipError_t launch_forward(int dtype, const void *src, const float *mv, const WarpShape &s,
                           void *out, uint8_t *mask, uint32_t *count, hipStream_t stream);
 
-// accum: float32 [N,C,H,W] image-gradient accumulator (grad_src itself for
-// float32 storage, else the workspace), or NULL. cast_to: storage-dtype
-// grad_src to round the accumulator into, or NULL (float32, or no grad_src).
+// grad_src / grad_mv may each be NULL (not requested). The workspace is used
+// only when grad_src is requested.
 hipError_t launch_backward(int dtype, const void *src, const float *mv, const WarpShape &s,
-                           const void *grad_out, float *accum, void *cast_to, float *grad_mv,
-                           hipStream_t stream);
-
-hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t stream);
+                           const void *grad_out, void *grad_src, float *grad_mv,
+                           const BwdWorkspace &ws, hipStream_t stream);
 
 }  // namespace exw

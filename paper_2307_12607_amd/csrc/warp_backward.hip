@@ -1,0 +1,695 @@
+// Adjoint of the motion-vector warp for CDNA4 (gfx950): gradients with
+// respect to the source frames (transpose of the bilinear gather) and to the
+// motion vectors (derivative of the bilinear blend), summed over phases.
+//
+// The image gradient is a scatter: each valid output pixel sends weight * g
+// to its four taps. Float atomics on MI355X top out near 0.3 G lane-ops per
+// ns even fully coalesced, and each one is a write to memory, so the scatter
+// is turned into a gather instead:
+//
+//   pass 1 (footprint): one wavefront per 64-pixel row segment of the output
+//     reads the segment's motion and records the bounding box of all its
+//     taps over all phases, plus the per-frame largest distance between a
+//     segment and its box. Pixels with no valid phase get a zero motion
+//     gradient here.
+//   pass 2 (tiles): one workgroup owns a 128 x TH tile of the image
+//     gradient. It walks the segments whose boxes reach the tile (only
+//     those within the per-frame distance can), recomputes their taps,
+//     accumulates weight * g for the taps inside the tile with LDS atomics,
+//     and stores the finished tile with plain coalesced stores: no global
+//     atomics, no zero fill. A pixel's motion gradient is computed by the
+//     one tile that holds the top-left tap of its first valid phase.
+//   pass 3 (far): segments whose box lies more than kFar pixels away are left
+//     to a fallback that uses global atomics (frames without such segments
+//     cost one check). For 16-bit storage such frames accumulate in a float32
+//     workspace and pass 4 rounds it into the output.
+#include <climits>
+
+#include "launch.h"
+#include "warp_common.h"
+
+namespace exw {
+namespace {
+
+constexpr int kTileW = 128;      // width of an image-gradient tile (pass 2)
+constexpr int kThreads = 256;    // four wavefronts
+constexpr int kFar = 128;        // segments reaching further use the atomic fallback
+constexpr int kFarBlocks = 1024; // grid of the fallback and cast passes
+
+struct Box {
+    int x_lo, x_hi, y_lo, y_hi;  // inclusive; x_lo > x_hi when the segment has no valid tap
+};
+
+struct FrameInfo {
+    int reach;    // largest distance (px) between a near segment and its box
+    int has_far;  // 1 if a segment of this frame reaches further than kFar
+};
+
+template <typename T>
+struct BwdArgs {
+    const T *src;
+    const float *mv;
+    const T *gout;
+    T *gsrc;          // image gradient in the storage type, or NULL
+    float *gmv;       // motion gradient, or NULL
+    float *accum32;   // float32 accumulator for 16-bit frames with far segments
+    Box *boxes;       // [N][H][segs]
+    FrameInfo *info;  // [N]
+    int n, c, h, w, k;
+    int segs;         // segments per row
+    int tile_h, tiles_x, tiles_y;
+    float s[4];
+};
+
+__device__ __forceinline__ int box_reach(const Box &b, int sx0, int row) {
+    const int r = max(max(sx0 - b.x_lo, b.x_hi - (sx0 + kSegW - 1)),
+                      max(row - b.y_lo, b.y_hi - row));
+    return max(r, 0);
+}
+
+// ---------------------------------------------------------------- pass 1
+
+constexpr int kFootRows = 4;  // rows handled by one wavefront of the footprint pass
+
+// One wavefront covers kFootRows rows of one 64-pixel column strip: all motion
+// loads are issued first, then the per-row boxes are reduced across lanes.
+template <int KT>
+__global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, float *gmv,
+                                                             Box *boxes, FrameInfo *info, int n,
+                                                             int h, int w, int segs,
+                                                             Phases4 ph) {
+    const int wave = threadIdx.x / kSegW;
+    const int lane = threadIdx.x % kSegW;
+    const int row_groups = (h + kFootRows - 1) / kFootRows;
+    const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kThreads / kSegW) + wave;
+    const int64_t total = static_cast<int64_t>(n) * row_groups * segs;
+    if (unit >= total) return;  // whole wavefront leaves together
+    const int sc = static_cast<int>(unit % segs);
+    const int64_t rg = unit / segs;
+    const int y0 = static_cast<int>(rg % row_groups) * kFootRows;
+    const int in = static_cast<int>(rg / row_groups);
+    const int sx0 = sc * kSegW;
+    const int x = sx0 + lane;
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const float *mu = mv + (2 * static_cast<int64_t>(in)) * hw;
+    const float *mvv = mu + hw;
+
+    float u[kFootRows], v[kFootRows];
+#pragma unroll
+    for (int r = 0; r < kFootRows; ++r) {
+        const bool in_r = x < w && y0 + r < h;
+        const int64_t p = static_cast<int64_t>(y0 + r) * w + x;
+        u[r] = in_r ? mu[p] : 0.0f;
+        v[r] = in_r ? mvv[p] : 0.0f;
+    }
+    int xl[kFootRows], xh[kFootRows], yl[kFootRows], yh[kFootRows];
+#pragma unroll
+    for (int r = 0; r < kFootRows; ++r) {
+        const int y = y0 + r;
+        const bool in_r = x < w && y < h;
+        xl[r] = INT_MAX; xh[r] = INT_MIN; yl[r] = INT_MAX; yh[r] = INT_MIN;
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < KT; ++j) {
+            const Axis ax = split_axis(ph.s[j] * u[r], x, w);
+            const Axis ay = split_axis(ph.s[j] * v[r], y, h);
+            if (in_r && ax.ok && ay.ok) {
+                any = true;
+                xl[r] = min(xl[r], ax.i0);
+                xh[r] = max(xh[r], ax.i1);
+                yl[r] = min(yl[r], ay.i0);
+                yh[r] = max(yh[r], ay.i1);
+            }
+        }
+        if (in_r && !any && gmv) {
+            const int64_t p = static_cast<int64_t>(y) * w + x;
+            gmv[(2 * static_cast<int64_t>(in)) * hw + p] = 0.0f;
+            gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = 0.0f;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kFootRows; ++r) {
+        xl[r] = wave_min(xl[r]);
+        xh[r] = wave_max(xh[r]);
+        yl[r] = wave_min(yl[r]);
+        yh[r] = wave_max(yh[r]);
+    }
+    int reach_max = -1, far = 0;
+    if (lane < kFootRows && y0 + lane < h) {
+        // lane r stores row r's box (selected without dynamic register indexing)
+        int bxl = xl[0], bxh = xh[0], byl = yl[0], byh = yh[0];
+#pragma unroll
+        for (int r = 1; r < kFootRows; ++r)
+            if (lane == r) { bxl = xl[r]; bxh = xh[r]; byl = yl[r]; byh = yh[r]; }
+        Box b{bxl, bxh, byl, byh};
+        if (bxl > bxh) {
+            b = Box{1, 0, 1, 0};
+        } else {
+            const int rr = box_reach(b, sx0, y0 + lane);
+            if (rr > kFar) far = 1; else reach_max = rr;
+        }
+        boxes[(static_cast<int64_t>(in) * h + y0 + lane) * segs + sc] = b;
+    }
+    reach_max = wave_max(reach_max);
+    far = wave_max(far);
+    if (lane == 0) {
+        if (far) atomicMax(&info[in].has_far, 1);
+        if (reach_max > __hip_atomic_load(&info[in].reach, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&info[in].reach, reach_max);  // rare: the value only grows
+    }
+}
+
+// ---------------------------------------------------------------- pass 2
+
+// Per-pixel taps of one phase.
+struct PTaps {
+    Axis ax, ay;
+    bool valid;
+};
+
+template <typename T, int CT>
+__device__ __forceinline__ void motion_grad_phase(const T *img, int64_t hw, int w, const PTaps &t,
+                                                  const float *g, float s, float &gu, float &gv) {
+    const int xl = min(t.ax.i0, w - 2);
+    const bool last = t.ax.i0 == w - 1;
+    const T *r0 = img + static_cast<int64_t>(t.ay.i0) * w + xl;
+    const T *r1 = img + static_cast<int64_t>(t.ay.i1) * w + xl;
+    const float fx = t.ax.f, fy = t.ay.f;
+    float su = 0.0f, sv = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < CT; ++ch) {
+        float a0, b0, a1, b1;
+        if (w >= 2) {
+            load_pair(r0 + ch * hw, a0, b0);
+            load_pair(r1 + ch * hw, a1, b1);
+        } else {  // single-column frame: both horizontal taps are column 0
+            a0 = b0 = to_f32(img[ch * hw + static_cast<int64_t>(t.ay.i0) * w]);
+            a1 = b1 = to_f32(img[ch * hw + static_cast<int64_t>(t.ay.i1) * w]);
+        }
+        const float i00 = last ? b0 : a0, i01 = b0;
+        const float i10 = last ? b1 : a1, i11 = b1;
+        const float dsx = fmaf(fy, i11 - i10, (1.0f - fy) * (i01 - i00));
+        const float dsy = fmaf(fx, i11 - i01, (1.0f - fx) * (i10 - i00));
+        su = fmaf(g[ch], dsx, su);
+        sv = fmaf(g[ch], dsy, sv);
+    }
+    // sx = x - s*u, so d sx / d u = -s (and likewise for v)
+    gu = fmaf(-s, su, gu);
+    gv = fmaf(-s, sv, gv);
+}
+
+// v from lane - 1 (0 into lane 0): a DPP wavefront shift.
+__device__ __forceinline__ float shift_up1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+// One wavefront owns a kTileW x TH tile of the image gradient and keeps it in
+// LDS; no other wavefront touches that LDS, so no barriers are needed.
+//
+// Accumulation: for one segment and phase, the lanes whose integer tap
+// offset (x - x0, y - y0) equals that of the first valid lane ("uniform"
+// lanes) hit pairwise distinct cells, and lane j's right-hand taps land on
+// lane j+1's left-hand cells. Each lane therefore adds, without atomics, its
+// own left taps plus its left neighbour's right taps to the cell at its own
+// uniform position (one read-add-write per row and channel); lane 63 also
+// adds its right taps one cell further. Lanes with another offset (motion
+// boundaries, random motion) add their taps with LDS atomics. LDS float
+// atomics serialise per lane on this hardware, so the uniform path is the
+// one that must carry the bulk of the work.
+template <typename T, int CT, int KT>
+__global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
+    extern __shared__ float acc[];  // [C][TH][kTileW]
+    const int C = CT;
+    const int TH = a.tile_h;
+    const int w = a.w, h = a.h;
+    const int lane = threadIdx.x;
+
+    const int b = xcd_tile_index(blockIdx.x, gridDim.x);
+    const int tx = b % a.tiles_x;
+    const int rest = b / a.tiles_x;
+    const int ty = rest % a.tiles_y;
+    const int in = rest / a.tiles_y;
+    const int tx0 = tx * kTileW, ty0 = ty * TH;
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const T *img = a.src ? a.src + static_cast<int64_t>(in) * C * hw : nullptr;
+    const float *mu = a.mv + (2 * static_cast<int64_t>(in)) * hw;
+    const float *mvv = mu + hw;
+    const FrameInfo fi = a.info[in];
+    const int reach = min(fi.reach, kFar);
+
+    for (int i = lane; i < C * TH * kTileW; i += kSegW) acc[i] = 0.0f;
+
+    // Segments that can reach this tile: rows within `reach`, and columns
+    // whose 64-pixel span lies within `reach` of the tile.
+    const int r_lo = max(0, ty0 - reach);
+    const int r_hi = min(h - 1, ty0 + TH - 1 + reach);
+    const int ca = tx0 - (kSegW - 1) - reach;
+    const int sc_lo = ca > 0 ? (ca + kSegW - 1) / kSegW : 0;
+    const int sc_hi = min(a.segs - 1, (tx0 + kTileW - 1 + reach) / kSegW);
+    const int nsc = sc_hi - sc_lo + 1;
+    const int total = (r_hi - r_lo + 1) * nsc;
+    const Box *fboxes = a.boxes + static_cast<int64_t>(in) * h * a.segs;
+
+    for (int base = 0; base < total; base += kSegW) {
+        bool hit = false;
+        {
+            const int i = base + lane;
+            if (i < total) {
+                const int r = r_lo + i / nsc;
+                const int sc = sc_lo + i % nsc;
+                const Box bx = fboxes[static_cast<int64_t>(r) * a.segs + sc];
+                hit = bx.x_lo <= bx.x_hi && box_reach(bx, sc * kSegW, r) <= kFar &&
+                      bx.x_hi >= tx0 && bx.x_lo < tx0 + kTileW && bx.y_hi >= ty0 &&
+                      bx.y_lo < ty0 + TH;
+            }
+        }
+        unsigned long long m = __ballot(hit);
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            const int i = base + j;  // wave-uniform
+            const int y = r_lo + i / nsc;
+            const int sx0 = (sc_lo + i % nsc) * kSegW;
+            const int x = sx0 + lane;
+            const bool inx = x < w;
+            const int64_t p = static_cast<int64_t>(y) * w + x;
+            const float u = inx ? mu[p] : 0.0f;
+            const float v = inx ? mvv[p] : 0.0f;
+            PTaps t[KT];
+            int first = -1;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                t[k].ax = split_axis(a.s[k] * u, x, w);
+                t[k].ay = split_axis(a.s[k] * v, y, h);
+                t[k].valid = inx && t[k].ax.ok && t[k].ay.ok;
+                if (first < 0 && t[k].valid) first = k;
+            }
+            bool owner = false;
+            if (a.gmv && first >= 0) {
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    if (k == first)
+                        owner = (unsigned)(t[k].ax.i0 - tx0) < (unsigned)kTileW &&
+                                (unsigned)(t[k].ay.i0 - ty0) < (unsigned)TH;
+            }
+            float gu = 0.0f, gv = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                const bool valid = t[k].valid;
+                const int lx0 = t[k].ax.i0 - tx0, lx1 = t[k].ax.i1 - tx0;
+                const int ly0 = t[k].ay.i0 - ty0, ly1 = t[k].ay.i1 - ty0;
+                const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
+                const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
+                const bool iny0 = (unsigned)ly0 < (unsigned)TH;
+                const bool iny1 = (unsigned)ly1 < (unsigned)TH;
+                const bool any = valid && (inx0 || inx1) && (iny0 || iny1);
+                const bool mine = owner && valid;  // this phase adds to the motion gradient
+                const unsigned long long any_m = __ballot(any);
+                if (any_m == 0ull && !__any(mine)) continue;  // wave-uniform
+                float g[CT];
+                const T *gp = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw + p;
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) g[ch] = (any || mine) ? to_f32(gp[ch * hw]) : 0.0f;
+                if (mine) motion_grad_phase<T, CT>(img, hw, w, t[k], g, a.s[k], gu, gv);
+                if (any_m == 0ull) continue;
+                // Uniform offset: that of the first lane with an in-tile tap.
+                const int offx = x - t[k].ax.i0, offy = y - t[k].ay.i0;
+                const int src_lane = __builtin_ctzll(any_m);
+                const int rx = __builtin_amdgcn_readlane(offx, src_lane);
+                const int ry = __builtin_amdgcn_readlane(offy, src_lane);
+                const bool uni = any && offx == rx && offy == ry;
+                const float fx = t[k].ax.f, fy = t[k].ay.f;
+                const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+                const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+                // Cells of the uniform pattern at this lane.
+                const int ux = x - rx - tx0;
+                const int uy0 = y - ry - ty0, uy1 = uy0 + 1;
+                const bool cx = (unsigned)ux < (unsigned)kTileW;
+                const bool cx1 = (unsigned)(ux + 1) < (unsigned)kTileW;
+                const bool cy0 = (unsigned)uy0 < (unsigned)TH;
+                const bool cy1 = (unsigned)uy1 < (unsigned)TH;
+                const bool edge = lane == kSegW - 1;
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) {
+                    float *pl = acc + ch * TH * kTileW;
+                    const float c00 = uni ? w00 * g[ch] : 0.0f;
+                    const float c01 = uni ? w01 * g[ch] : 0.0f;
+                    const float c10 = uni ? w10 * g[ch] : 0.0f;
+                    const float c11 = uni ? w11 * g[ch] : 0.0f;
+                    const float top = c00 + shift_up1(c01);
+                    const float bot = c10 + shift_up1(c11);
+                    if (cx && cy0) pl[uy0 * kTileW + ux] += top;
+                    if (cx && cy1) pl[uy1 * kTileW + ux] += bot;
+                    if (edge && cx1 && cy0) pl[uy0 * kTileW + ux + 1] += c01;
+                    if (edge && cx1 && cy1) pl[uy1 * kTileW + ux + 1] += c11;
+                    if (any && !uni) {
+                        if (inx0 && iny0 && w00 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx0, w00 * g[ch]);
+                        if (inx1 && iny0 && w01 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx1, w01 * g[ch]);
+                        if (inx0 && iny1 && w10 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx0, w10 * g[ch]);
+                        if (inx1 && iny1 && w11 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx1, w11 * g[ch]);
+                    }
+                }
+            }
+            if (owner) {
+                a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
+                a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;
+            }
+        }
+    }
+
+    if (!a.gsrc) return;
+    // Store the finished tile. 16-bit frames that also receive far-segment
+    // atomics go through the float32 accumulator instead.
+    const bool to_accum = fi.has_far && a.accum32 != nullptr;
+    for (int i = lane; i < C * TH * kTileW; i += kSegW) {
+        const int ch = i / (TH * kTileW);
+        const int rem = i % (TH * kTileW);
+        const int X = tx0 + rem % kTileW, Y = ty0 + rem / kTileW;
+        if (X >= w || Y >= h) continue;
+        const int64_t o = (static_cast<int64_t>(in) * C + ch) * hw + static_cast<int64_t>(Y) * w + X;
+        if (to_accum)
+            a.accum32[o] = acc[i];
+        else
+            a.gsrc[o] = from_f32<T>(acc[i]);
+    }
+}
+
+// ---------------------------------------------------------------- pass 3
+
+// Far segments: scatter with global float32 atomics, motion gradient per pixel.
+template <typename T, int CT, int KT>
+__global__ __launch_bounds__(kThreads) void adjoint_far_kernel(BwdArgs<T> a, float *accum) {
+    const int C = CT, w = a.w, h = a.h;
+    const int wave = threadIdx.x / kSegW, lane = threadIdx.x % kSegW;
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const int64_t per_frame = static_cast<int64_t>(h) * a.segs;
+    for (int in = 0; in < a.n; ++in) {
+        if (!a.info[in].has_far) continue;  // uniform across the grid
+        const T *img = a.src ? a.src + static_cast<int64_t>(in) * C * hw : nullptr;
+        float *acc = accum ? accum + static_cast<int64_t>(in) * C * hw : nullptr;
+        for (int64_t sg = static_cast<int64_t>(blockIdx.x) * (kThreads / kSegW) + wave;
+             sg < per_frame; sg += static_cast<int64_t>(gridDim.x) * (kThreads / kSegW)) {
+            const int y = static_cast<int>(sg / a.segs);
+            const int sx0 = static_cast<int>(sg % a.segs) * kSegW;
+            const Box bx = a.boxes[static_cast<int64_t>(in) * per_frame + sg];
+            if (bx.x_lo > bx.x_hi || box_reach(bx, sx0, y) <= kFar) continue;
+            const int x = sx0 + lane;
+            if (x >= w) continue;
+            const int64_t p = static_cast<int64_t>(y) * w + x;
+            const float u = a.mv[(2 * static_cast<int64_t>(in)) * hw + p];
+            const float v = a.mv[(2 * static_cast<int64_t>(in) + 1) * hw + p];
+            float gu = 0.0f, gv = 0.0f;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                PTaps t;
+                t.ax = split_axis(a.s[k] * u, x, w);
+                t.ay = split_axis(a.s[k] * v, y, h);
+                if (!(t.ax.ok && t.ay.ok)) continue;
+                any = true;
+                const T *gp = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw + p;
+                float g[CT];
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) g[ch] = to_f32(gp[ch * hw]);
+                if (acc) {
+                    const float fx = t.ax.f, fy = t.ay.f;
+                    const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+                    const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+                    const int64_t r0 = static_cast<int64_t>(t.ay.i0) * w;
+                    const int64_t r1 = static_cast<int64_t>(t.ay.i1) * w;
+#pragma unroll
+                    for (int ch = 0; ch < CT; ++ch) {
+                        float *pl = acc + ch * hw;
+                        if (w00 != 0.0f) atomicAdd(pl + r0 + t.ax.i0, w00 * g[ch]);
+                        if (w01 != 0.0f) atomicAdd(pl + r0 + t.ax.i1, w01 * g[ch]);
+                        if (w10 != 0.0f) atomicAdd(pl + r1 + t.ax.i0, w10 * g[ch]);
+                        if (w11 != 0.0f) atomicAdd(pl + r1 + t.ax.i1, w11 * g[ch]);
+                    }
+                }
+                if (a.gmv) motion_grad_phase<T, CT>(img, hw, w, t, g, a.s[k], gu, gv);
+            }
+            if (a.gmv && any) {
+                a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
+                a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pass 4
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cast_far_frames_kernel(const float *accum32, T *gsrc,
+                                                                   const FrameInfo *info, int n,
+                                                                   int64_t frame_elems) {
+    for (int in = 0; in < n; ++in) {
+        if (!info[in].has_far) continue;
+        const float *s = accum32 + static_cast<int64_t>(in) * frame_elems;
+        T *d = gsrc + static_cast<int64_t>(in) * frame_elems;
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+             i < frame_elems; i += static_cast<int64_t>(gridDim.x) * kThreads)
+            d[i] = from_f32<T>(s[i]);
+    }
+}
+
+// ---------------------------------------------------------------- motion only
+
+// Motion gradient alone (no image gradient requested): per pixel, no atomics.
+template <typename T, int CT, int KT>
+__global__ __launch_bounds__(kThreads) void motion_grad_kernel(BwdArgs<T> a) {
+    const int w = a.w, h = a.h;
+    const int64_t seg = static_cast<int64_t>(blockIdx.x) * (kThreads / kSegW) + threadIdx.x / kSegW;
+    const int64_t per_frame = static_cast<int64_t>(h) * a.segs;
+    if (seg >= per_frame * a.n) return;
+    const int in = static_cast<int>(seg / per_frame);
+    const int64_t sg = seg % per_frame;
+    const int y = static_cast<int>(sg / a.segs);
+    const int x = static_cast<int>(sg % a.segs) * kSegW + static_cast<int>(threadIdx.x % kSegW);
+    if (x >= w) return;
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const int64_t p = static_cast<int64_t>(y) * w + x;
+    const T *img = a.src + static_cast<int64_t>(in) * CT * hw;
+    const float u = a.mv[(2 * static_cast<int64_t>(in)) * hw + p];
+    const float v = a.mv[(2 * static_cast<int64_t>(in) + 1) * hw + p];
+    float gu = 0.0f, gv = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        PTaps t;
+        t.ax = split_axis(a.s[k] * u, x, w);
+        t.ay = split_axis(a.s[k] * v, y, h);
+        if (!(t.ax.ok && t.ay.ok)) continue;
+        const T *gp = a.gout + (static_cast<int64_t>(in) * KT + k) * CT * hw + p;
+        float g[CT];
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) g[ch] = to_f32(gp[ch * hw]);
+        motion_grad_phase<T, CT>(img, hw, w, t, g, a.s[k], gu, gv);
+    }
+    a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
+    a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;
+}
+
+
+// ---------------------------------------------------------------- any C
+
+// Channel counts without a specialised path: scatter with global float32
+// atomics into a zeroed accumulator, motion gradient per pixel.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void adjoint_generic_kernel(BwdArgs<T> a, float *accum) {
+    const int C = a.c, w = a.w, h = a.h;
+    const int64_t seg = static_cast<int64_t>(blockIdx.x) * (kThreads / kSegW) + threadIdx.x / kSegW;
+    const int64_t per_frame = static_cast<int64_t>(h) * a.segs;
+    if (seg >= per_frame * a.n) return;
+    const int in = static_cast<int>(seg / per_frame);
+    const int64_t sg = seg % per_frame;
+    const int y = static_cast<int>(sg / a.segs);
+    const int x = static_cast<int>(sg % a.segs) * kSegW + static_cast<int>(threadIdx.x % kSegW);
+    if (x >= w) return;
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const int64_t p = static_cast<int64_t>(y) * w + x;
+    const T *img = a.src ? a.src + static_cast<int64_t>(in) * C * hw : nullptr;
+    float *acc = accum ? accum + static_cast<int64_t>(in) * C * hw : nullptr;
+    const float u = a.mv[(2 * static_cast<int64_t>(in)) * hw + p];
+    const float v = a.mv[(2 * static_cast<int64_t>(in) + 1) * hw + p];
+    float gu = 0.0f, gv = 0.0f;
+    for (int k = 0; k < a.k; ++k) {
+        const Axis ax = split_axis(a.s[k] * u, x, w);
+        const Axis ay = split_axis(a.s[k] * v, y, h);
+        if (!(ax.ok && ay.ok)) continue;
+        const float fx = ax.f, fy = ay.f;
+        const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+        const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+        const int64_t r0 = static_cast<int64_t>(ay.i0) * w;
+        const int64_t r1 = static_cast<int64_t>(ay.i1) * w;
+        const T *gp = a.gout + (static_cast<int64_t>(in) * a.k + k) * C * hw + p;
+        float su = 0.0f, sv = 0.0f;
+        for (int ch = 0; ch < C; ++ch) {
+            const float g = to_f32(gp[ch * hw]);
+            if (acc) {
+                float *pl = acc + ch * hw;
+                if (w00 != 0.0f) atomicAdd(pl + r0 + ax.i0, w00 * g);
+                if (w01 != 0.0f) atomicAdd(pl + r0 + ax.i1, w01 * g);
+                if (w10 != 0.0f) atomicAdd(pl + r1 + ax.i0, w10 * g);
+                if (w11 != 0.0f) atomicAdd(pl + r1 + ax.i1, w11 * g);
+            }
+            if (a.gmv) {
+                const T *pl = img + ch * hw;
+                const float i00 = to_f32(pl[r0 + ax.i0]), i01 = to_f32(pl[r0 + ax.i1]);
+                const float i10 = to_f32(pl[r1 + ax.i0]), i11 = to_f32(pl[r1 + ax.i1]);
+                const float dsx = fmaf(fy, i11 - i10, (1.0f - fy) * (i01 - i00));
+                const float dsy = fmaf(fx, i11 - i01, (1.0f - fx) * (i10 - i00));
+                su = fmaf(g, dsx, su);
+                sv = fmaf(g, dsy, sv);
+            }
+        }
+        gu = fmaf(-a.s[k], su, gu);
+        gv = fmaf(-a.s[k], sv, gv);
+    }
+    if (a.gmv) {
+        a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
+        a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void zero_f32_kernel(float *p, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        p[i] = 0.0f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void cast_all_kernel(const float *s, T *d, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        d[i] = from_f32<T>(s[i]);
+}
+
+template <typename T>
+hipError_t run_generic(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
+    const int64_t segs_total = static_cast<int64_t>(a.n) * a.h * a.segs;
+    const unsigned seg_blocks =
+        static_cast<unsigned>((segs_total + kThreads / kSegW - 1) / (kThreads / kSegW));
+    const int64_t elems = static_cast<int64_t>(a.n) * a.c * a.h * a.w;
+    float *accum = nullptr;
+    if (a.gsrc) {
+        accum = ws.accum32 ? ws.accum32 : reinterpret_cast<float *>(a.gsrc);
+        hipLaunchKernelGGL(zero_f32_kernel, dim3(kFarBlocks * 4), dim3(kThreads), 0, st, accum,
+                           elems);
+    }
+    hipLaunchKernelGGL(adjoint_generic_kernel<T>, dim3(seg_blocks), dim3(kThreads), 0, st, a,
+                       accum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.gsrc || !ws.accum32) return e;
+    hipLaunchKernelGGL(cast_all_kernel<T>, dim3(kFarBlocks * 4), dim3(kThreads), 0, st,
+                       ws.accum32, a.gsrc, elems);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- launchers
+
+int tile_rows_for(int c) {
+    // One wavefront per 128 x 4 tile: 2 KB of float32 accumulators per
+    // channel (8 KB for RGBA, 24 KB for a 12-channel G-buffer).
+    (void)c;
+    return 4;
+}
+
+template <typename T, int CT, int KT>
+hipError_t run(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
+    const int64_t segs_total = static_cast<int64_t>(a.n) * a.h * a.segs;
+    const unsigned seg_blocks =
+        static_cast<unsigned>((segs_total + kThreads / kSegW - 1) / (kThreads / kSegW));
+    if (!a.gsrc) {  // motion gradient only
+        hipLaunchKernelGGL((motion_grad_kernel<T, CT, KT>), dim3(seg_blocks), dim3(kThreads), 0,
+                           st, a);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(a.info),
+                                   static_cast<int64_t>(a.n) * 2, st);
+    if (e != hipSuccess) return e;
+    Phases4 ph;
+    for (int j = 0; j < 4; ++j) ph.s[j] = a.s[j];
+    const int64_t foot_units =
+        static_cast<int64_t>(a.n) * ((a.h + kFootRows - 1) / kFootRows) * a.segs;
+    const unsigned foot_blocks =
+        static_cast<unsigned>((foot_units + kThreads / kSegW - 1) / (kThreads / kSegW));
+    hipLaunchKernelGGL((footprint_kernel<KT>), dim3(foot_blocks), dim3(kThreads), 0, st, a.mv,
+                       a.gmv, a.boxes, a.info, a.n, a.h, a.w, a.segs, ph);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    const size_t lds = sizeof(float) * CT * a.tile_h * kTileW;
+    const int64_t tiles = static_cast<int64_t>(a.n) * a.tiles_x * a.tiles_y;
+    hipLaunchKernelGGL((adjoint_tiles_kernel<T, CT, KT>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(kSegW), lds, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    float *far_accum = ws.accum32 ? ws.accum32 : reinterpret_cast<float *>(a.gsrc);
+    hipLaunchKernelGGL((adjoint_far_kernel<T, CT, KT>), dim3(kFarBlocks), dim3(kThreads), 0, st,
+                       a, far_accum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ws.accum32) {
+        hipLaunchKernelGGL(cast_far_frames_kernel<T>, dim3(kFarBlocks), dim3(kThreads), 0, st,
+                           ws.accum32, a.gsrc, a.info, a.n,
+                           static_cast<int64_t>(a.c) * a.h * a.w);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+template <typename T, int CT>
+hipError_t run_k(const BwdArgs<T> &a, const BwdWorkspace &ws, hipStream_t st) {
+    switch (a.k) {
+    case 1: return run<T, CT, 1>(a, ws, st);
+    case 2: return run<T, CT, 2>(a, ws, st);
+    case 3: return run<T, CT, 3>(a, ws, st);
+    default: return run<T, CT, 4>(a, ws, st);
+    }
+}
+
+template <typename T>
+hipError_t run_typed(const void *src, const float *mv, const WarpShape &s, const void *gout,
+                     void *gsrc, float *gmv, const BwdWorkspace &ws, hipStream_t st) {
+    BwdArgs<T> a;
+    a.src = static_cast<const T *>(src);
+    a.mv = mv;
+    a.gout = static_cast<const T *>(gout);
+    a.gsrc = static_cast<T *>(gsrc);
+    a.gmv = gmv;
+    a.accum32 = ws.accum32;
+    a.boxes = reinterpret_cast<Box *>(ws.boxes);
+    a.info = reinterpret_cast<FrameInfo *>(ws.info);
+    a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
+    a.segs = (s.w + kSegW - 1) / kSegW;
+    a.tile_h = tile_rows_for(s.c);
+    a.tiles_x = (s.w + kTileW - 1) / kTileW;
+    a.tiles_y = (s.h + a.tile_h - 1) / a.tile_h;
+    for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
+    switch (s.c) {
+    case 1: return run_k<T, 1>(a, ws, st);
+    case 2: return run_k<T, 2>(a, ws, st);
+    case 3: return run_k<T, 3>(a, ws, st);
+    case 4: return run_k<T, 4>(a, ws, st);
+    case 12: return run_k<T, 12>(a, ws, st);
+    default: return run_generic<T>(a, ws, st);
+    }
+}
+
+}  // namespace
+
+size_t backward_box_bytes(int n, int h, int w) {
+    return sizeof(Box) * static_cast<size_t>(n) * h * ((w + kSegW - 1) / kSegW);
+}
+
+size_t backward_info_bytes(int n) { return sizeof(FrameInfo) * static_cast<size_t>(n); }
+
+hipError_t launch_backward(int dtype, const void *src, const float *mv, const WarpShape &s,
+                           const void *grad_out, void *grad_src, float *grad_mv,
+                           const BwdWorkspace &ws, hipStream_t stream) {
+    switch (dtype) {
+    case 0: return run_typed<float>(src, mv, s, grad_out, grad_src, grad_mv, ws, stream);
+    case 1: return run_typed<_Float16>(src, mv, s, grad_out, grad_src, grad_mv, ws, stream);
+    default: return run_typed<__bf16>(src, mv, s, grad_out, grad_src, grad_mv, ws, stream);
+    }
+}
+
+}  // namespace exw

@@ -1,0 +1,252 @@
+// Forward motion-vector warp for CDNA4 (gfx950).
+//
+// What is computed (paper §II-B image warping; §IV-B: the predicted frames
+// P_1..P_3 shown at t + i/4 all come from F_t; §III-B: warped pixels without
+// a source in the frame are invalid): each output pixel reads its motion
+// vector once, forms all K phase displacements, gathers the four bilinear
+// taps of every channel, and writes K output pixels, K mask bytes and the
+// per-(frame, phase) invalid counts.
+//
+// Layout of the work: one wavefront = 64 consecutive pixels of a row, four
+// wavefronts per workgroup (a 64 x 4 tile), tiles renumbered per XCD. Motion,
+// output and mask accesses are coalesced; the taps of neighbouring lanes fall
+// on neighbouring addresses wherever the motion is locally smooth, and the
+// two horizontal taps of a row come in one (unaligned) load. All gathers of
+// all phases are issued before any store, so a wavefront waits for one
+// gather round trip, not K. HBM traffic measured on this kernel equals the
+// algorithmic bytes (no halo re-reads reach HBM), so there is no LDS staging:
+// the L2 already serves the overlap between tiles. No MFMA: this is a gather.
+#include "launch.h"
+#include "warp_common.h"
+
+namespace exw {
+namespace {
+
+constexpr int kTileW = 64;
+constexpr int kTileH = 4;
+constexpr int kThreads = kTileW * kTileH;
+
+template <typename T>
+struct FwdArgs {
+    const T *src;
+    const float *mv;
+    T *out;
+    uint8_t *mask;
+    uint32_t *count;
+    int n, c, h, w, k;
+    int tiles_x, tiles_y;
+    float s[4];
+};
+
+struct PixelPos {
+    int in, x, y;
+    bool inside;
+};
+
+__device__ __forceinline__ PixelPos decode_pixel(int tiles_x, int tiles_y, int w, int h) {
+    const int b = xcd_tile_index(blockIdx.x, gridDim.x);
+    const int tx = b % tiles_x;
+    const int rest = b / tiles_x;
+    PixelPos q;
+    q.in = rest / tiles_y;
+    q.x = tx * kTileW + threadIdx.x;
+    q.y = (rest % tiles_y) * kTileH + threadIdx.y;
+    q.inside = (q.x < w) && (q.y < h);
+    return q;
+}
+
+__device__ __forceinline__ void count_invalid(uint32_t *count, int64_t plane, bool inside,
+                                              bool valid) {
+    // One atomic per wavefront that saw invalid pixels (frame borders only).
+    const unsigned long long bal = __ballot(inside && !valid);
+    if (bal != 0ull && __lane_id() == 0)
+        atomicAdd(count + plane, static_cast<uint32_t>(__popcll(bal)));
+}
+
+// Channel count CT and phase count KT known at compile time; requires W >= 2
+// (paired horizontal loads).
+template <typename T, int CT, int KT>
+__global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
+    const int w = a.w, h = a.h;
+    const PixelPos q = decode_pixel(a.tiles_x, a.tiles_y, w, h);
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const int64_t p = static_cast<int64_t>(q.y) * w + q.x;
+
+    float u = 0.0f, v = 0.0f;
+    if (q.inside) {
+        u = a.mv[(2 * static_cast<int64_t>(q.in)) * hw + p];
+        v = a.mv[(2 * static_cast<int64_t>(q.in) + 1) * hw + p];
+    }
+    const T *img = a.src + static_cast<int64_t>(q.in) * CT * hw;
+
+    Axis ax[KT], ay[KT];
+    bool valid[KT];
+    float i00[KT][CT], i01[KT][CT], i10[KT][CT], i11[KT][CT];
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        ax[j] = split_axis(a.s[j] * u, q.x, w);
+        ay[j] = split_axis(a.s[j] * v, q.y, h);
+        valid[j] = q.inside && ax[j].ok && ay[j].ok;
+        // The pair (xl, xl + 1) must stay in the row: at the last column the
+        // pair starts one to the left and the tap takes its second element.
+        const int xl = min(ax[j].i0, w - 2);
+        const bool last = ax[j].i0 == w - 1;
+        const T *r0 = img + static_cast<int64_t>(ay[j].i0) * w + xl;
+        const T *r1 = img + static_cast<int64_t>(ay[j].i1) * w + xl;
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) {
+            float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
+            if (valid[j]) {
+                load_pair(r0 + ch * hw, a0, b0);
+                load_pair(r1 + ch * hw, a1, b1);
+            }
+            i00[j][ch] = last ? b0 : a0;
+            i01[j][ch] = b0;
+            i10[j][ch] = last ? b1 : a1;
+            i11[j][ch] = b1;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        const int64_t plane = static_cast<int64_t>(q.in) * KT + j;
+        if (q.inside) {
+            const float fx = ax[j].f, fy = ay[j].f;
+            const float w00 = (1.0f - fx) * (1.0f - fy);
+            const float w01 = fx * (1.0f - fy);
+            const float w10 = (1.0f - fx) * fy;
+            const float w11 = fx * fy;
+            T *o = a.out + plane * CT * hw + p;
+#pragma unroll
+            for (int ch = 0; ch < CT; ++ch) {
+                float acc = w00 * i00[j][ch];
+                acc = fmaf(w01, i01[j][ch], acc);
+                acc = fmaf(w10, i10[j][ch], acc);
+                acc = fmaf(w11, i11[j][ch], acc);
+                o[ch * hw] = from_f32<T>(valid[j] ? acc : 0.0f);
+            }
+            if (a.mask) a.mask[plane * hw + p] = valid[j] ? 1 : 0;
+        }
+        if (a.count) count_invalid(a.count, plane, q.inside, valid[j]);
+    }
+}
+
+// Any channel count, any phase count, any width (including W == 1): one
+// channel at a time, scalar taps.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void warp_forward_generic_kernel(FwdArgs<T> a) {
+    const int C = a.c, w = a.w, h = a.h;
+    const PixelPos q = decode_pixel(a.tiles_x, a.tiles_y, w, h);
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const int64_t p = static_cast<int64_t>(q.y) * w + q.x;
+    float u = 0.0f, v = 0.0f;
+    if (q.inside) {
+        u = a.mv[(2 * static_cast<int64_t>(q.in)) * hw + p];
+        v = a.mv[(2 * static_cast<int64_t>(q.in) + 1) * hw + p];
+    }
+    const T *img = a.src + static_cast<int64_t>(q.in) * C * hw;
+    for (int j = 0; j < a.k; ++j) {
+        const Axis ax = split_axis(a.s[j] * u, q.x, w);
+        const Axis ay = split_axis(a.s[j] * v, q.y, h);
+        const bool valid = q.inside && ax.ok && ay.ok;
+        const int64_t plane = static_cast<int64_t>(q.in) * a.k + j;
+        if (q.inside) {
+            T *o = a.out + plane * C * hw + p;
+            const float w00 = (1.0f - ax.f) * (1.0f - ay.f);
+            const float w01 = ax.f * (1.0f - ay.f);
+            const float w10 = (1.0f - ax.f) * ay.f;
+            const float w11 = ax.f * ay.f;
+            const int64_t r0 = static_cast<int64_t>(ay.i0) * w;
+            const int64_t r1 = static_cast<int64_t>(ay.i1) * w;
+            for (int ch = 0; ch < C; ++ch) {
+                float acc = 0.0f;
+                if (valid) {
+                    const T *pl = img + ch * hw;
+                    acc = w00 * to_f32(pl[r0 + ax.i0]);
+                    acc = fmaf(w01, to_f32(pl[r0 + ax.i1]), acc);
+                    acc = fmaf(w10, to_f32(pl[r1 + ax.i0]), acc);
+                    acc = fmaf(w11, to_f32(pl[r1 + ax.i1]), acc);
+                }
+                o[ch * hw] = from_f32<T>(acc);
+            }
+            if (a.mask) a.mask[plane * hw + p] = valid ? 1 : 0;
+        }
+        if (a.count) count_invalid(a.count, plane, q.inside, valid);
+    }
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+         t += stride)
+        p[t] = 0u;
+}
+
+template <typename T>
+FwdArgs<T> make_args(const void *src, const float *mv, const WarpShape &s, void *out,
+                     uint8_t *mask, uint32_t *count) {
+    FwdArgs<T> a;
+    a.src = static_cast<const T *>(src);
+    a.mv = mv;
+    a.out = static_cast<T *>(out);
+    a.mask = mask;
+    a.count = count;
+    a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
+    a.tiles_x = (s.w + kTileW - 1) / kTileW;
+    a.tiles_y = (s.h + kTileH - 1) / kTileH;
+    for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
+    return a;
+}
+
+template <typename T, int CT>
+hipError_t launch_ck(const FwdArgs<T> &a, dim3 grid, hipStream_t st) {
+    switch (a.k) {
+    case 1: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 1>), grid, dim3(kTileW, kTileH), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 2>), grid, dim3(kTileW, kTileH), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 3>), grid, dim3(kTileW, kTileH), 0, st, a); break;
+    default: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 4>), grid, dim3(kTileW, kTileH), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_typed(const void *src, const float *mv, const WarpShape &s, void *out,
+                        uint8_t *mask, uint32_t *count, hipStream_t st) {
+    const FwdArgs<T> a = make_args<T>(src, mv, s, out, mask, count);
+    const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(a.tiles_x) * a.tiles_y * s.n));
+    if (s.w >= 2) {
+        switch (s.c) {
+        case 1: return launch_ck<T, 1>(a, grid, st);
+        case 3: return launch_ck<T, 3>(a, grid, st);
+        case 4: return launch_ck<T, 4>(a, grid, st);
+        case 12: return launch_ck<T, 12>(a, grid, st);
+        default: break;
+        }
+    }
+    hipLaunchKernelGGL(warp_forward_generic_kernel<T>, grid, dim3(kTileW, kTileH), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t stream) {
+    int64_t blocks = (count + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(int dtype, const void *src, const float *mv, const WarpShape &s,
+                          void *out, uint8_t *mask, uint32_t *count, hipStream_t stream) {
+    if (count) {
+        hipError_t e = launch_zero_u32(count, static_cast<int64_t>(s.n) * s.k, stream);
+        if (e != hipSuccess) return e;
+    }
+    switch (dtype) {
+    case 0: return launch_typed<float>(src, mv, s, out, mask, count, stream);
+    case 1: return launch_typed<_Float16>(src, mv, s, out, mask, count, stream);
+    default: return launch_typed<__bf16>(src, mv, s, out, mask, count, stream);
+    }
+}
+
+}  // namespace exw

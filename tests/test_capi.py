@@ -61,7 +61,8 @@ def fwd(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=None,
 
 
 def bwd(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=None, k=1,
-        gout=FAKE + (2 << 30), gsrc=FAKE + (3 << 30), gmv=FAKE + (4 << 30), ws=None, ws_bytes=0):
+        gout=FAKE + (2 << 30), gsrc=FAKE + (3 << 30), gmv=FAKE + (4 << 30), ws=FAKE + (6 << 30),
+        ws_bytes=1 << 30):
     if phases is None:
         phases = _phases(1.0)
     return _capi.lib().exw_warp_backward_batched(src, dtype, n, c, h, w, mv, phases, k, gout,
@@ -106,8 +107,11 @@ def test_forward_rejects(kwargs, status, needle):
     (dict(gout=None), INVALID, "grad_out is NULL"),
     (dict(src=None), INVALID, "src is NULL"),
     (dict(mv=None), INVALID, "mv is NULL"),
+    (dict(ws=None), INVALID, "workspace is NULL"),
     (dict(dtype=1, ws=None), INVALID, "workspace is NULL"),
-    (dict(dtype=2, ws=FAKE + (6 << 30), ws_bytes=16), INVALID, "needs"),
+    (dict(dtype=2, ws_bytes=16), INVALID, "needs"),
+    (dict(ws=FAKE + (6 << 30) + 128), INVALID, "256-byte aligned"),
+    (dict(ws=FAKE + (3 << 30) + 512), INVALID, "overlaps output workspace"),
     (dict(gsrc=FAKE + (2 << 30)), INVALID, "grad_src overlaps input grad_out"),
     (dict(gmv=FAKE), INVALID, "grad_mv overlaps input src"),
     (dict(gmv=FAKE + (3 << 30) + 64), INVALID, "grad_src overlaps output grad_mv"),
@@ -131,10 +135,16 @@ def test_empty_batches_and_no_requested_gradient_are_no_ops():
 
 def test_workspace_size():
     L = _capi.lib()
-    assert L.exw_warp_backward_workspace_bytes(0, 2, 3, 4, 5) == 0
-    assert L.exw_warp_backward_workspace_bytes(1, 2, 3, 4, 5) == 4 * 2 * 3 * 4 * 5
-    assert L.exw_warp_backward_workspace_bytes(2, 8, 12, 1440, 2560) == 4 * 8 * 12 * 1440 * 2560
+    # boxes: 16 B per 64-pixel row segment; 8 B per frame; float32 accumulator for 16-bit storage
+    def expect(dtype, n, c, h, w):
+        boxes = 16 * n * h * ((w + 63) // 64)
+        info = (boxes + 255) // 256 * 256
+        accum = (info + 8 * n + 255) // 256 * 256
+        return accum + (0 if dtype == 0 else 4 * n * c * h * w)
+    for args in [(0, 2, 3, 4, 5), (1, 2, 3, 4, 5), (2, 8, 12, 1440, 2560), (0, 8, 4, 1080, 1920)]:
+        assert L.exw_warp_backward_workspace_bytes(*args) == expect(*args), args
     assert L.exw_warp_backward_workspace_bytes(2, 0, 3, 4, 5) == 0
+    assert L.exw_warp_backward_workspace_bytes(9, 1, 3, 4, 5) == 0
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -231,3 +231,58 @@ def test_full_size_backward_sampled(index, dtype):
         else:
             bound = half_ulp(ref_s, dtype) + GRAD_TOL * np.maximum(1.0, np.abs(ref_s))
             assert (np.abs(got_s - ref_s) <= bound).all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_far_motion_fallback(dtype):
+    """Motion reaching further than the tile gather covers (> 128 px) goes
+    through the atomic fallback; mixed with near motion in the same frame."""
+    dev = need_gpu()
+    rng = np.random.default_rng(20)
+    n, c, h, w = 2, 4, 150, 400
+    src = rng.random((n, c, h, w), dtype=np.float32)
+    mv = rng.uniform(-3, 3, (n, 2, h, w)).astype(np.float32)
+    mv[0, 0, 40:60, 100:300] = rng.uniform(-250, 250, (20, 200)).astype(np.float32)
+    mv[0, 1, 70:75, :] = 140.5
+    phases = [0.25, 0.5, 1.0]
+    g = rng.standard_normal((n, 3, c, h, w)).astype(np.float32)
+    announce("far motion", dtype)
+    gs, gm = grads_gpu(src, mv, phases, g, dtype, dev)
+    ref_gs, ref_gm = warp_oracle.backward(stored(src, dtype), mv, phases, stored(g, dtype))
+    check_grad(gm, ref_gm, f"grad_mv far {dtype}")
+    if dtype == "f32":
+        check_grad(gs, ref_gs, "grad_src far")
+    else:
+        bound = half_ulp(ref_gs, dtype) + GRAD_TOL * np.maximum(1.0, np.abs(ref_gs))
+        assert (np.abs(gs - ref_gs) <= bound).all()
+
+
+def test_backward_shapes_channels_and_partial_requests():
+    dev = need_gpu()
+    rng = np.random.default_rng(21)
+    for (n, c, h, w, k) in [(1, 1, 1, 1, 1), (2, 2, 7, 1, 3), (3, 5, 5, 65, 4),
+                            (1, 12, 9, 130, 1), (1, 64, 3, 5, 1), (2, 3, 67, 257, 2),
+                            (1, 4, 1, 300, 3)]:
+        src = rng.random((n, c, h, w), dtype=np.float32)
+        mv = rng.uniform(-3, 3, (n, 2, h, w)).astype(np.float32)
+        phases = [0.25, 0.5, 0.75, 1.0][:k]
+        g = rng.standard_normal((n, k, c, h, w)).astype(np.float32)
+        for dtype in ("f32", "bf16"):
+            announce("backward shapes", n, c, h, w, k, dtype)
+            ref_gs, ref_gm = warp_oracle.backward(stored(src, dtype), mv, phases, stored(g, dtype))
+            gs, gm = grads_gpu(src, mv, phases, g, dtype, dev)
+            check_grad(gm, ref_gm, f"grad_mv {(n, c, h, w, k)} {dtype}")
+            if dtype == "f32":
+                check_grad(gs, ref_gs, f"grad_src {(n, c, h, w, k)}")
+            else:
+                bound = half_ulp(ref_gs, dtype) + GRAD_TOL * np.maximum(1.0, np.abs(ref_gs))
+                assert (np.abs(gs - ref_gs) <= bound).all(), (n, c, h, w, k)
+            # one gradient at a time
+            sd, gd = to_dev(src, dtype, dev), to_dev(g, dtype, dev)
+            md = torch.from_numpy(mv).to(dev)
+            only_s, none_m = exw.warp_backward(sd, md, phases, gd, need_mv=False)
+            none_s, only_m = exw.warp_backward(sd, md, phases, gd, need_src=False)
+            assert none_m is None and none_s is None
+            check_grad(to_host(only_m), ref_gm, "motion only")
+            if dtype == "f32":
+                check_grad(to_host(only_s), ref_gs, "image only")
