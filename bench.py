@@ -26,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-KERNEL_SRC = os.path.join(ROOT, "paper_2307_12607_amd", "csrc", "warp_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2307_12607_amd", "csrc")
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("warp_common.h", "warp_forward.hip",
+                                               "warp_backward.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
 
@@ -54,8 +56,12 @@ def algorithmic_bytes(n, c, h, w, k, b):
 
 
 def source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel sources: stored counter readings apply only to these."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):

@@ -88,16 +88,9 @@ __device__ __forceinline__ void load_pair(const T *p, float &a, float &b) {
     b = half_bits_to_f32(v >> 16, static_cast<T *>(nullptr));
 }
 
-// Wavefront-wide min / max (64 lanes) by butterfly shuffles.
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
+// Wavefront-wide min / max over all 64 lanes (DPP + readlane, result in every
+// lane; every lane must be active).
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
 }  // namespace exw
