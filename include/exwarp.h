@@ -96,7 +96,7 @@ const char *exw_last_error(void);
  *   phases: host array of k finite floats (s = i/4 in the method; any finite
  *           value is accepted, 0 gives the identity).
  *   k: 1..EXW_MAX_PHASES.   n >= 0, 1 <= c <= EXW_MAX_CHANNELS, h, w >= 0,
- *   h*w < 2^31.
+ *   h*w <= 2^30.
  *   mask: optional [N,K,H,W] uint8 output, or NULL.
  *   invalid_count: optional [N,K] uint32 output (number of invalid pixels
  *           per frame and phase, paper §III-C holes statistic restricted to

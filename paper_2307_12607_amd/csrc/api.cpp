@@ -82,9 +82,10 @@ exw_status check_common(exw_dtype dtype, int32_t n, int32_t c, int32_t h, int32_
     // Frame coordinates must be exact in float32 and a plane index must fit int32.
     if (h >= (1 << 24) || w >= (1 << 24))
         return fail(EXW_ERROR_UNSUPPORTED, "frame side >= 2^24 (h=%d, w=%d)", h, w);
+    // In-plane byte offsets are 32-bit in the kernels.
     ck->hw = uint64_t(h) * uint64_t(w);
-    if (ck->hw >= (uint64_t(1) << 31))
-        return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu >= 2^31", (unsigned long long)ck->hw);
+    if (ck->hw > (uint64_t(1) << 30))
+        return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu > 2^30", (unsigned long long)ck->hw);
     ck->img_elems = uint64_t(n) * uint64_t(c) * ck->hw;
     ck->out_elems = ck->img_elems * uint64_t(k);
     ck->mv_elems = uint64_t(n) * 2u * ck->hw;

@@ -98,9 +98,9 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, fl
 #pragma unroll
     for (int r = 0; r < kFootRows; ++r) {
         const bool in_r = x < w && y0 + r < h;
-        const int64_t p = static_cast<int64_t>(y0 + r) * w + x;
-        u[r] = in_r ? mu[p] : 0.0f;
-        v[r] = in_r ? mvv[p] : 0.0f;
+        const uint32_t p = static_cast<uint32_t>(y0 + r) * static_cast<uint32_t>(w) + x;
+        u[r] = in_r ? *at(mu, p) : 0.0f;
+        v[r] = in_r ? *at(mvv, p) : 0.0f;
     }
     int xl[kFootRows], xh[kFootRows], yl[kFootRows], yh[kFootRows];
 #pragma unroll
@@ -173,19 +173,20 @@ __device__ __forceinline__ void motion_grad_phase(const T *img, int64_t hw, int 
                                                   const float *g, float s, float &gu, float &gv) {
     const int xl = min(t.ax.i0, w - 2);
     const bool last = t.ax.i0 == w - 1;
-    const T *r0 = img + static_cast<int64_t>(t.ay.i0) * w + xl;
-    const T *r1 = img + static_cast<int64_t>(t.ay.i1) * w + xl;
+    const uint32_t o0 = static_cast<uint32_t>(t.ay.i0) * static_cast<uint32_t>(w) + xl;
+    const uint32_t o1 = static_cast<uint32_t>(t.ay.i1) * static_cast<uint32_t>(w) + xl;
     const float fx = t.ax.f, fy = t.ay.f;
     float su = 0.0f, sv = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < CT; ++ch) {
+        const T *pl = img + ch * hw;
         float a0, b0, a1, b1;
         if (w >= 2) {
-            load_pair(r0 + ch * hw, a0, b0);
-            load_pair(r1 + ch * hw, a1, b1);
+            load_pair(at(pl, o0), a0, b0);
+            load_pair(at(pl, o1), a1, b1);
         } else {  // single-column frame: both horizontal taps are column 0
-            a0 = b0 = to_f32(img[ch * hw + static_cast<int64_t>(t.ay.i0) * w]);
-            a1 = b1 = to_f32(img[ch * hw + static_cast<int64_t>(t.ay.i1) * w]);
+            a0 = b0 = to_f32(*at(pl, static_cast<uint32_t>(t.ay.i0)));
+            a1 = b1 = to_f32(*at(pl, static_cast<uint32_t>(t.ay.i1)));
         }
         const float i00 = last ? b0 : a0, i01 = b0;
         const float i10 = last ? b1 : a1, i11 = b1;
@@ -219,7 +220,7 @@ __device__ __forceinline__ float shift_up1(float v) {
 // one that must carry the bulk of the work.
 template <typename T, int CT, int KT>
 __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
-    extern __shared__ float acc[];  // [C][TH][kTileW]
+    extern __shared__ float acc[];  // [C][TH][kTileW], then one dummy word
     const int C = CT;
     const int TH = a.tile_h;
     const int w = a.w, h = a.h;
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     const FrameInfo fi = a.info[in];
     const int reach = min(fi.reach, kFar);
 
-    for (int i = lane; i < C * TH * kTileW; i += kSegW) acc[i] = 0.0f;
+    for (int i = lane; i < C * TH * kTileW + 1; i += kSegW) acc[i] = 0.0f;
 
     // Segments that can reach this tile: rows within `reach`, and columns
     // whose 64-pixel span lies within `reach` of the tile.
@@ -273,9 +274,9 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
             const int sx0 = (sc_lo + i % nsc) * kSegW;
             const int x = sx0 + lane;
             const bool inx = x < w;
-            const int64_t p = static_cast<int64_t>(y) * w + x;
-            const float u = inx ? mu[p] : 0.0f;
-            const float v = inx ? mvv[p] : 0.0f;
+            const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + x;
+            const float u = inx ? *at(mu, p) : 0.0f;
+            const float v = inx ? *at(mvv, p) : 0.0f;
             PTaps t[KT];
             int first = -1;
 #pragma unroll
@@ -308,9 +309,9 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                 const unsigned long long any_m = __ballot(any);
                 if (any_m == 0ull && !__any(mine)) continue;  // wave-uniform
                 float g[CT];
-                const T *gp = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw + p;
+                const T *gk = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw;
 #pragma unroll
-                for (int ch = 0; ch < CT; ++ch) g[ch] = (any || mine) ? to_f32(gp[ch * hw]) : 0.0f;
+                for (int ch = 0; ch < CT; ++ch) g[ch] = (any || mine) ? to_f32(*at(gk + ch * hw, p)) : 0.0f;
                 if (mine) motion_grad_phase<T, CT>(img, hw, w, t[k], g, a.s[k], gu, gv);
                 if (any_m == 0ull) continue;
                 // Uniform offset: that of the first lane with an in-tile tap.
@@ -322,38 +323,74 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                 const float fx = t[k].ax.f, fy = t[k].ay.f;
                 const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
                 const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
-                // Cells of the uniform pattern at this lane.
+                // Cells of the uniform pattern at this lane; lanes whose cell is
+                // outside the tile read and write a dummy word (adding 0), so the
+                // read-add-writes need no branches and can be batched.
                 const int ux = x - rx - tx0;
                 const int uy0 = y - ry - ty0, uy1 = uy0 + 1;
                 const bool cx = (unsigned)ux < (unsigned)kTileW;
-                const bool cx1 = (unsigned)(ux + 1) < (unsigned)kTileW;
+                const bool cx1 = lane == kSegW - 1 && (unsigned)(ux + 1) < (unsigned)kTileW;
                 const bool cy0 = (unsigned)uy0 < (unsigned)TH;
                 const bool cy1 = (unsigned)uy1 < (unsigned)TH;
-                const bool edge = lane == kSegW - 1;
+                const int plane_sz = TH * kTileW;
+                const int dummy = CT * plane_sz;
+                const int i_top = cx && cy0 ? uy0 * kTileW + ux : dummy - 0;
+                const int i_bot = cx && cy1 ? uy1 * kTileW + ux : dummy - 0;
+                const int i_et = cx1 && cy0 ? uy0 * kTileW + ux + 1 : dummy - 0;
+                const int i_eb = cx1 && cy1 ? uy1 * kTileW + ux + 1 : dummy - 0;
+                float c01[CT], c11[CT], top[CT], bot[CT];
 #pragma unroll
                 for (int ch = 0; ch < CT; ++ch) {
-                    float *pl = acc + ch * TH * kTileW;
-                    const float c00 = uni ? w00 * g[ch] : 0.0f;
-                    const float c01 = uni ? w01 * g[ch] : 0.0f;
-                    const float c10 = uni ? w10 * g[ch] : 0.0f;
-                    const float c11 = uni ? w11 * g[ch] : 0.0f;
-                    const float top = c00 + shift_up1(c01);
-                    const float bot = c10 + shift_up1(c11);
-                    if (cx && cy0) pl[uy0 * kTileW + ux] += top;
-                    if (cx && cy1) pl[uy1 * kTileW + ux] += bot;
-                    if (edge && cx1 && cy0) pl[uy0 * kTileW + ux + 1] += c01;
-                    if (edge && cx1 && cy1) pl[uy1 * kTileW + ux + 1] += c11;
+                    const float gg = uni ? g[ch] : 0.0f;
+                    c01[ch] = w01 * gg;
+                    c11[ch] = w11 * gg;
+                    top[ch] = fmaf(w00, gg, shift_up1(c01[ch]));
+                    bot[ch] = fmaf(w10, gg, shift_up1(c11[ch]));
+                }
+                // Dummy indices stay at the single dummy word for every channel.
+#define EXW_CELL(i, ch) ((i) == dummy ? dummy : (ch) * plane_sz + (i))
+                float rt[CT], rb[CT];
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) {
+                    rt[ch] = acc[EXW_CELL(i_top, ch)];
+                    rb[ch] = acc[EXW_CELL(i_bot, ch)];
+                }
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) {
+                    acc[EXW_CELL(i_top, ch)] = rt[ch] + (cx && cy0 ? top[ch] : 0.0f);
+                    acc[EXW_CELL(i_bot, ch)] = rb[ch] + (cx && cy1 ? bot[ch] : 0.0f);
+                }
+                if (__ballot(cx1 && (cy0 || cy1))) {  // lane 63's right-hand taps
+#pragma unroll
+                    for (int ch = 0; ch < CT; ++ch) {
+                        rt[ch] = acc[EXW_CELL(i_et, ch)];
+                        rb[ch] = acc[EXW_CELL(i_eb, ch)];
+                    }
+#pragma unroll
+                    for (int ch = 0; ch < CT; ++ch) {
+                        acc[EXW_CELL(i_et, ch)] = rt[ch] + (cx1 && cy0 ? c01[ch] : 0.0f);
+                        acc[EXW_CELL(i_eb, ch)] = rb[ch] + (cx1 && cy1 ? c11[ch] : 0.0f);
+                    }
+                }
+#undef EXW_CELL
+                // Lanes off the uniform pattern (motion boundaries): LDS atomics.
+                if (__ballot(any && !uni)) {
                     if (any && !uni) {
-                        if (inx0 && iny0 && w00 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx0, w00 * g[ch]);
-                        if (inx1 && iny0 && w01 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx1, w01 * g[ch]);
-                        if (inx0 && iny1 && w10 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx0, w10 * g[ch]);
-                        if (inx1 && iny1 && w11 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx1, w11 * g[ch]);
+#pragma unroll
+                        for (int ch = 0; ch < CT; ++ch) {
+                            float *pl = acc + ch * plane_sz;
+                            if (inx0 && iny0 && w00 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx0, w00 * g[ch]);
+                            if (inx1 && iny0 && w01 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx1, w01 * g[ch]);
+                            if (inx0 && iny1 && w10 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx0, w10 * g[ch]);
+                            if (inx1 && iny1 && w11 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx1, w11 * g[ch]);
+                        }
                     }
                 }
             }
             if (owner) {
-                a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
-                a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;
+                float *gm = a.gmv + 2 * static_cast<int64_t>(in) * hw;
+                *at(gm, p) = gu;
+                *at(gm + hw, p) = gv;
             }
         }
     }
@@ -367,11 +404,12 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         const int rem = i % (TH * kTileW);
         const int X = tx0 + rem % kTileW, Y = ty0 + rem / kTileW;
         if (X >= w || Y >= h) continue;
-        const int64_t o = (static_cast<int64_t>(in) * C + ch) * hw + static_cast<int64_t>(Y) * w + X;
+        const int64_t plane = (static_cast<int64_t>(in) * C + ch) * hw;
+        const uint32_t o = static_cast<uint32_t>(Y) * static_cast<uint32_t>(w) + X;
         if (to_accum)
-            a.accum32[o] = acc[i];
+            *at(a.accum32 + plane, o) = acc[i];
         else
-            a.gsrc[o] = from_f32<T>(acc[i]);
+            *at(a.gsrc + plane, o) = from_f32<T>(acc[i]);
     }
 }
 
@@ -588,10 +626,11 @@ hipError_t run_generic(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
 // ---------------------------------------------------------------- launchers
 
 int tile_rows_for(int c) {
-    // One wavefront per 128 x 4 tile: 2 KB of float32 accumulators per
-    // channel (8 KB for RGBA, 24 KB for a 12-channel G-buffer).
+    // One wavefront per 128 x 2 tile: 1 KB of float32 accumulators per
+    // channel (4 KB for RGBA, 12 KB for a 12-channel G-buffer); measured
+    // faster than 128 x 4, 128 x 1 and 64 x 2 (more wavefronts in flight).
     (void)c;
-    return 4;
+    return 2;
 }
 
 template <typename T, int CT, int KT>
@@ -617,7 +656,7 @@ hipError_t run(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
                        a.gmv, a.boxes, a.info, a.n, a.h, a.w, a.segs, ph);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    const size_t lds = sizeof(float) * CT * a.tile_h * kTileW;
+    const size_t lds = sizeof(float) * (CT * a.tile_h * kTileW + 1);  // + dummy word
     const int64_t tiles = static_cast<int64_t>(a.n) * a.tiles_x * a.tiles_y;
     hipLaunchKernelGGL((adjoint_tiles_kernel<T, CT, KT>), dim3(static_cast<unsigned>(tiles)),
                        dim3(kSegW), lds, st, a);

@@ -59,6 +59,21 @@ __device__ __forceinline__ Axis split_axis(float d, int p, int size) {
     return a;
 }
 
+// Element `i` of a plane whose base pointer is uniform across the wavefront:
+// the byte offset is formed in 32 bits (the C-ABI caps a plane at 2^30
+// pixels, 4 GB of float32), so the access can use a scalar base register plus
+// a 32-bit vector offset instead of 64-bit vector address arithmetic.
+template <typename T>
+__device__ __forceinline__ const T *at(const T *base, uint32_t i) {
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                       i * static_cast<uint32_t>(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T *at(T *base, uint32_t i) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) +
+                                 i * static_cast<uint32_t>(sizeof(T)));
+}
+
 // Two horizontally adjacent stored values p[0], p[1] in one load. The address
 // is only element-aligned; gfx950 serves unaligned global loads.
 typedef float f32x2_u __attribute__((ext_vector_type(2), aligned(4)));

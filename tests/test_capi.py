@@ -93,7 +93,7 @@ INVALID, UNSUPPORTED = _capi.EXW_ERROR_INVALID_VALUE, _capi.EXW_ERROR_UNSUPPORTE
     (dict(count=FAKE + (1 << 30) + 8), INVALID, "overlaps input mv"),
     (dict(count=FAKE + 2 + (5 << 30)), INVALID, "aligned"),
     (dict(h=1 << 24, w=1), UNSUPPORTED, "2^24"),
-    (dict(h=1 << 16, w=1 << 16), UNSUPPORTED, "2^31"),
+    (dict(h=1 << 16, w=1 << 15), UNSUPPORTED, "2^30"),
     (dict(n=1 << 20, c=64, h=4096, w=4096, k=1), UNSUPPORTED, "too large"),
 ])
 def test_forward_rejects(kwargs, status, needle):
