@@ -294,32 +294,48 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                         owner = (unsigned)(t[k].ax.i0 - tx0) < (unsigned)kTileW &&
                                 (unsigned)(t[k].ay.i0 - ty0) < (unsigned)TH;
             }
-            float gu = 0.0f, gv = 0.0f;
+            // Which phases touch the tile (or feed this lane's motion gradient);
+            // all their upstream-gradient loads are issued together.
+            bool any[KT], mine[KT];
+            float g[KT][CT];
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                const bool valid = t[k].valid;
+                const bool inx0 = (unsigned)(t[k].ax.i0 - tx0) < (unsigned)kTileW;
+                const bool inx1 = (unsigned)(t[k].ax.i1 - tx0) < (unsigned)kTileW;
+                const bool iny0 = (unsigned)(t[k].ay.i0 - ty0) < (unsigned)TH;
+                const bool iny1 = (unsigned)(t[k].ay.i1 - ty0) < (unsigned)TH;
+                any[k] = t[k].valid && (inx0 || inx1) && (iny0 || iny1);
+                mine[k] = owner && t[k].valid;
+                const T *gk = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw;
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch)
+                    g[k][ch] = (any[k] || mine[k]) ? to_f32(*at(gk + ch * hw, p)) : 0.0f;
+            }
+            if (owner) {
+                float gu = 0.0f, gv = 0.0f;
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    if (mine[k]) motion_grad_phase<T, CT>(img, hw, w, t[k], g[k], a.s[k], gu, gv);
+                float *gm = a.gmv + 2 * static_cast<int64_t>(in) * hw;
+                *at(gm, p) = gu;
+                *at(gm + hw, p) = gv;
+            }
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                const unsigned long long any_m = __ballot(any[k]);
+                if (any_m == 0ull) continue;  // wave-uniform
                 const int lx0 = t[k].ax.i0 - tx0, lx1 = t[k].ax.i1 - tx0;
                 const int ly0 = t[k].ay.i0 - ty0, ly1 = t[k].ay.i1 - ty0;
                 const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
                 const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
                 const bool iny0 = (unsigned)ly0 < (unsigned)TH;
                 const bool iny1 = (unsigned)ly1 < (unsigned)TH;
-                const bool any = valid && (inx0 || inx1) && (iny0 || iny1);
-                const bool mine = owner && valid;  // this phase adds to the motion gradient
-                const unsigned long long any_m = __ballot(any);
-                if (any_m == 0ull && !__any(mine)) continue;  // wave-uniform
-                float g[CT];
-                const T *gk = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw;
-#pragma unroll
-                for (int ch = 0; ch < CT; ++ch) g[ch] = (any || mine) ? to_f32(*at(gk + ch * hw, p)) : 0.0f;
-                if (mine) motion_grad_phase<T, CT>(img, hw, w, t[k], g, a.s[k], gu, gv);
-                if (any_m == 0ull) continue;
                 // Uniform offset: that of the first lane with an in-tile tap.
                 const int offx = x - t[k].ax.i0, offy = y - t[k].ay.i0;
                 const int src_lane = __builtin_ctzll(any_m);
                 const int rx = __builtin_amdgcn_readlane(offx, src_lane);
                 const int ry = __builtin_amdgcn_readlane(offy, src_lane);
-                const bool uni = any && offx == rx && offy == ry;
+                const bool uni = any[k] && offx == rx && offy == ry;
                 const float fx = t[k].ax.f, fy = t[k].ay.f;
                 const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
                 const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
@@ -334,14 +350,14 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                 const bool cy1 = (unsigned)uy1 < (unsigned)TH;
                 const int plane_sz = TH * kTileW;
                 const int dummy = CT * plane_sz;
-                const int i_top = cx && cy0 ? uy0 * kTileW + ux : dummy - 0;
-                const int i_bot = cx && cy1 ? uy1 * kTileW + ux : dummy - 0;
-                const int i_et = cx1 && cy0 ? uy0 * kTileW + ux + 1 : dummy - 0;
-                const int i_eb = cx1 && cy1 ? uy1 * kTileW + ux + 1 : dummy - 0;
+                const int i_top = cx && cy0 ? uy0 * kTileW + ux : dummy;
+                const int i_bot = cx && cy1 ? uy1 * kTileW + ux : dummy;
+                const int i_et = cx1 && cy0 ? uy0 * kTileW + ux + 1 : dummy;
+                const int i_eb = cx1 && cy1 ? uy1 * kTileW + ux + 1 : dummy;
                 float c01[CT], c11[CT], top[CT], bot[CT];
 #pragma unroll
                 for (int ch = 0; ch < CT; ++ch) {
-                    const float gg = uni ? g[ch] : 0.0f;
+                    const float gg = uni ? g[k][ch] : 0.0f;
                     c01[ch] = w01 * gg;
                     c11[ch] = w11 * gg;
                     top[ch] = fmaf(w00, gg, shift_up1(c01[ch]));
@@ -374,23 +390,18 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                 }
 #undef EXW_CELL
                 // Lanes off the uniform pattern (motion boundaries): LDS atomics.
-                if (__ballot(any && !uni)) {
-                    if (any && !uni) {
+                if (__ballot(any[k] && !uni)) {
+                    if (any[k] && !uni) {
 #pragma unroll
                         for (int ch = 0; ch < CT; ++ch) {
                             float *pl = acc + ch * plane_sz;
-                            if (inx0 && iny0 && w00 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx0, w00 * g[ch]);
-                            if (inx1 && iny0 && w01 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx1, w01 * g[ch]);
-                            if (inx0 && iny1 && w10 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx0, w10 * g[ch]);
-                            if (inx1 && iny1 && w11 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx1, w11 * g[ch]);
+                            if (inx0 && iny0 && w00 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx0, w00 * g[k][ch]);
+                            if (inx1 && iny0 && w01 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx1, w01 * g[k][ch]);
+                            if (inx0 && iny1 && w10 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx0, w10 * g[k][ch]);
+                            if (inx1 && iny1 && w11 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx1, w11 * g[k][ch]);
                         }
                     }
                 }
-            }
-            if (owner) {
-                float *gm = a.gmv + 2 * static_cast<int64_t>(in) * hw;
-                *at(gm, p) = gu;
-                *at(gm + hw, p) = gv;
             }
         }
     }
