@@ -10,19 +10,18 @@
 //   pass 1 (footprint): one wavefront per 64-pixel row segment of the output
 //     reads the segment's motion and records the bounding box of all its
 //     taps over all phases, plus the per-frame largest distance between a
-//     segment and its box. Pixels with no valid phase get a zero motion
-//     gradient here.
-//   pass 2 (tiles): one workgroup owns a 128 x TH tile of the image
-//     gradient. It walks the segments whose boxes reach the tile (only
-//     those within the per-frame distance can), recomputes their taps,
-//     accumulates weight * g for the taps inside the tile with LDS atomics,
-//     and stores the finished tile with plain coalesced stores: no global
-//     atomics, no zero fill. A pixel's motion gradient is computed by the
-//     one tile that holds the top-left tap of its first valid phase.
+//     segment and its box.
+//   pass 2 (tiles): one wavefront owns a 128 x TH tile of the image gradient
+//     in LDS. It walks the segments whose boxes reach the tile (only those
+//     within the per-frame distance can), recomputes their taps, accumulates
+//     weight * g for the taps inside the tile, and stores the finished tile
+//     with plain coalesced stores: no global atomics, no zero fill. The tile
+//     that contains a segment ("home") also computes that segment's motion
+//     gradient, so every pixel's motion gradient is written exactly once.
 //   pass 3 (far): segments whose box lies more than kFar pixels away are left
-//     to a fallback that uses global atomics (frames without such segments
-//     cost one check). For 16-bit storage such frames accumulate in a float32
-//     workspace and pass 4 rounds it into the output.
+//     to a fallback that scatters with global atomics (frames without such
+//     segments cost one check). For 16-bit storage such frames accumulate in a
+//     float32 workspace and pass 4 rounds it into the output.
 #include <climits>
 
 #include "launch.h"
@@ -74,10 +73,9 @@ constexpr int kFootRows = 4;  // rows handled by one wavefront of the footprint 
 // One wavefront covers kFootRows rows of one 64-pixel column strip: all motion
 // loads are issued first, then the per-row boxes are reduced across lanes.
 template <int KT>
-__global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, float *gmv,
-                                                             Box *boxes, FrameInfo *info, int n,
-                                                             int h, int w, int segs,
-                                                             Phases4 ph) {
+__global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Box *boxes,
+                                                             FrameInfo *info, int n, int h, int w,
+                                                             int segs, Phases4 ph) {
     const int wave = threadIdx.x / kSegW;
     const int lane = threadIdx.x % kSegW;
     const int row_groups = (h + kFootRows - 1) / kFootRows;
@@ -108,23 +106,15 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, fl
         const int y = y0 + r;
         const bool in_r = x < w && y < h;
         xl[r] = INT_MAX; xh[r] = INT_MIN; yl[r] = INT_MAX; yh[r] = INT_MIN;
-        bool any = false;
 #pragma unroll
-        for (int j = 0; j < KT; ++j) {
+        for (int j = 0; j < KT; ++j) {  // branch-free: invalid phases leave the box as is
             const Axis ax = split_axis(ph.s[j] * u[r], x, w);
             const Axis ay = split_axis(ph.s[j] * v[r], y, h);
-            if (in_r && ax.ok && ay.ok) {
-                any = true;
-                xl[r] = min(xl[r], ax.i0);
-                xh[r] = max(xh[r], ax.i1);
-                yl[r] = min(yl[r], ay.i0);
-                yh[r] = max(yh[r], ay.i1);
-            }
-        }
-        if (in_r && !any && gmv) {
-            const int64_t p = static_cast<int64_t>(y) * w + x;
-            gmv[(2 * static_cast<int64_t>(in)) * hw + p] = 0.0f;
-            gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = 0.0f;
+            const bool ok = in_r && ax.ok && ay.ok;
+            xl[r] = min(xl[r], ok ? ax.i0 : INT_MAX);
+            xh[r] = max(xh[r], ok ? ax.i1 : INT_MIN);
+            yl[r] = min(yl[r], ok ? ay.i0 : INT_MAX);
+            yh[r] = max(yh[r], ok ? ay.i1 : INT_MIN);
         }
     }
 #pragma unroll
@@ -205,23 +195,84 @@ __device__ __forceinline__ float shift_up1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
 
+// Channels of one LDS cell: padded to a multiple of four (one 16-byte LDS
+// access per four channels) from three channels up.
+template <int CT>
+struct CellWidth {
+    static constexpr int value = CT <= 2 ? CT : ((CT + 3) / 4) * 4;
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <int CP>
+__device__ __forceinline__ void cell_read(const float *acc, int cell, float (&v)[CP]) {
+    if constexpr (CP % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < CP / 4; ++q) {
+            const f32x4 t = reinterpret_cast<const f32x4 *>(acc)[cell * (CP / 4) + q];
+            v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        }
+    } else if constexpr (CP == 2) {
+        const f32x2 t = reinterpret_cast<const f32x2 *>(acc)[cell];
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        v[0] = acc[cell];
+    }
+}
+
+template <int CP>
+__device__ __forceinline__ void cell_write(float *acc, int cell, const float (&v)[CP]) {
+    if constexpr (CP % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < CP / 4; ++q) {
+            f32x4 t;
+            t.x = v[4 * q]; t.y = v[4 * q + 1]; t.z = v[4 * q + 2]; t.w = v[4 * q + 3];
+            reinterpret_cast<f32x4 *>(acc)[cell * (CP / 4) + q] = t;
+        }
+    } else if constexpr (CP == 2) {
+        f32x2 t;
+        t.x = v[0]; t.y = v[1];
+        reinterpret_cast<f32x2 *>(acc)[cell] = t;
+    } else {
+        acc[cell] = v[0];
+    }
+}
+
+// What one replayed segment needs from global memory, loaded one segment
+// ahead of its use.
+template <typename T, int CT, int KT>
+struct SegLoad {
+    float u, v;
+    T g[KT][CT];
+};
+
 // One wavefront owns a kTileW x TH tile of the image gradient and keeps it in
-// LDS; no other wavefront touches that LDS, so no barriers are needed.
+// LDS as cells of CP consecutive channels, followed by one scratch cell per
+// lane (rows TH.. of the cell array, never stored). No other wavefront touches
+// that LDS, so no barriers are needed.
 //
-// Accumulation: for one segment and phase, the lanes whose integer tap
-// offset (x - x0, y - y0) equals that of the first valid lane ("uniform"
-// lanes) hit pairwise distinct cells, and lane j's right-hand taps land on
-// lane j+1's left-hand cells. Each lane therefore adds, without atomics, its
-// own left taps plus its left neighbour's right taps to the cell at its own
-// uniform position (one read-add-write per row and channel); lane 63 also
-// adds its right taps one cell further. Lanes with another offset (motion
-// boundaries, random motion) add their taps with LDS atomics. LDS float
-// atomics serialise per lane on this hardware, so the uniform path is the
-// one that must carry the bulk of the work.
+// Work list: the segments whose boxes reach the tile (only rows and columns
+// within the per-frame reach can), plus the tile's own segments ("home"),
+// which are replayed even when their taps lie elsewhere because the home tile
+// computes their motion gradient. Box loads run one batch of 64 candidates
+// ahead; motion and upstream-gradient loads run one segment ahead.
+//
+// Accumulation: for one segment and phase, the lanes whose integer tap offset
+// (x - x0, y - y0) equals that of the first lane with an in-tile tap
+// ("uniform" lanes) hit pairwise distinct cells, and lane j's right-hand taps
+// land on lane j+1's left-hand cells. Each lane therefore adds, without
+// atomics, its own left taps plus its left neighbour's right taps to its cell
+// of the uniform pattern (one read-add-write of the whole cell per row); lane
+// 63 also adds its right taps one cell further. Lanes whose cell lies outside
+// the tile use their scratch cell, so the read-add-writes need no branches.
+// Lanes with another offset (motion boundaries, random motion) add their taps
+// with LDS atomics, which serialise per lane on this hardware; the uniform path
+// must carry the bulk of the work.
 template <typename T, int CT, int KT>
 __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
-    extern __shared__ float acc[];  // [C][TH][kTileW], then one dummy word
-    const int C = CT;
+    extern __shared__ __attribute__((aligned(16))) float acc[];  // [TH * kTileW + kSegW][CP]
+    constexpr int CP = CellWidth<CT>::value;
     const int TH = a.tile_h;
     const int w = a.w, h = a.h;
     const int lane = threadIdx.x;
@@ -233,16 +284,19 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     const int in = rest / a.tiles_y;
     const int tx0 = tx * kTileW, ty0 = ty * TH;
     const int64_t hw = static_cast<int64_t>(h) * w;
-    const T *img = a.src ? a.src + static_cast<int64_t>(in) * C * hw : nullptr;
+    const T *img = a.src ? a.src + static_cast<int64_t>(in) * CT * hw : nullptr;
     const float *mu = a.mv + (2 * static_cast<int64_t>(in)) * hw;
     const float *mvv = mu + hw;
+    const T *gframe = a.gout + static_cast<int64_t>(in) * KT * CT * hw;
     const FrameInfo fi = a.info[in];
     const int reach = min(fi.reach, kFar);
+    const int ncells = TH * kTileW;
 
-    for (int i = lane; i < C * TH * kTileW + 1; i += kSegW) acc[i] = 0.0f;
+    for (int i = lane; i < (ncells + kSegW) * CP / 4; i += kSegW)
+        reinterpret_cast<f32x4 *>(acc)[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // Segments that can reach this tile: rows within `reach`, and columns
-    // whose 64-pixel span lies within `reach` of the tile.
+    // Candidate segments: rows within `reach` of the tile, and columns whose
+    // 64-pixel span lies within `reach` of it; the home segments are among them.
     const int r_lo = max(0, ty0 - reach);
     const int r_hi = min(h - 1, ty0 + TH - 1 + reach);
     const int ca = tx0 - (kSegW - 1) - reach;
@@ -252,181 +306,199 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     const int total = (r_hi - r_lo + 1) * nsc;
     const Box *fboxes = a.boxes + static_cast<int64_t>(in) * h * a.segs;
 
-    for (int base = 0; base < total; base += kSegW) {
-        bool hit = false;
-        {
-            const int i = base + lane;
-            if (i < total) {
-                const int r = r_lo + i / nsc;
-                const int sc = sc_lo + i % nsc;
-                const Box bx = fboxes[static_cast<int64_t>(r) * a.segs + sc];
-                hit = bx.x_lo <= bx.x_hi && box_reach(bx, sc * kSegW, r) <= kFar &&
-                      bx.x_hi >= tx0 && bx.x_lo < tx0 + kTileW && bx.y_hi >= ty0 &&
-                      bx.y_lo < ty0 + TH;
-            }
+    auto box_of = [&](int i) -> Box {  // clamped: the load is always in bounds
+        const int ic = min(i, total - 1);
+        return fboxes[static_cast<int64_t>(r_lo + ic / nsc) * a.segs + sc_lo + ic % nsc];
+    };
+    // Bit 0: the segment is near (its taps are scattered here); bit 1: home.
+    auto classify = [&](const Box &bx, int i) -> int {
+        if (i >= total) return 0;
+        const int r = r_lo + i / nsc, sc = sc_lo + i % nsc;
+        const bool home = a.gmv && (unsigned)(r - ty0) < (unsigned)TH && sc * kSegW / kTileW == tx;
+        const bool near = bx.x_lo <= bx.x_hi && box_reach(bx, sc * kSegW, r) <= kFar &&
+                          bx.x_hi >= tx0 && bx.x_lo < tx0 + kTileW && bx.y_hi >= ty0 &&
+                          bx.y_lo < ty0 + TH;
+        return (near ? 1 : 0) | (home ? 2 : 0);
+    };
+
+    int base = 0;
+    Box nb = box_of(lane);
+    unsigned long long m_hit = 0, m_near = 0;
+    // Next segment to replay as (candidate << 1) | near, or -1 when done.
+    auto next_seg = [&]() -> int {
+        while (m_hit == 0) {
+            if (base >= total) return -1;
+            const int cls = classify(nb, base + lane);
+            m_hit = __ballot(cls != 0);
+            m_near = __ballot(cls & 1);
+            base += kSegW;
+            if (base < total) nb = box_of(base + lane);
         }
-        unsigned long long m = __ballot(hit);
-        while (m) {
-            const int j = __builtin_ctzll(m);
-            m &= m - 1;
-            const int i = base + j;  // wave-uniform
-            const int y = r_lo + i / nsc;
-            const int sx0 = (sc_lo + i % nsc) * kSegW;
-            const int x = sx0 + lane;
-            const bool inx = x < w;
-            const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + x;
-            const float u = inx ? *at(mu, p) : 0.0f;
-            const float v = inx ? *at(mvv, p) : 0.0f;
-            PTaps t[KT];
-            int first = -1;
+        const int j = __builtin_ctzll(m_hit);
+        m_hit &= m_hit - 1;
+        return ((base - kSegW + j) << 1) | static_cast<int>((m_near >> j) & 1ull);
+    };
+    auto load_seg = [&](int code, SegLoad<T, CT, KT> &d) {
+        const int i = code >> 1;
+        const int y = r_lo + i / nsc;
+        const int x = (sc_lo + i % nsc) * kSegW + lane;
+        // lanes past the row end read its last pixel (always in bounds)
+        const uint32_t pc = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + min(x, w - 1);
+        d.u = *at(mu, pc);
+        d.v = *at(mvv, pc);
 #pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                t[k].ax = split_axis(a.s[k] * u, x, w);
-                t[k].ay = split_axis(a.s[k] * v, y, h);
-                t[k].valid = inx && t[k].ax.ok && t[k].ay.ok;
-                if (first < 0 && t[k].valid) first = k;
-            }
-            bool owner = false;
-            if (a.gmv && first >= 0) {
+        for (int k = 0; k < KT; ++k)
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    if (k == first)
-                        owner = (unsigned)(t[k].ax.i0 - tx0) < (unsigned)kTileW &&
-                                (unsigned)(t[k].ay.i0 - ty0) < (unsigned)TH;
-            }
-            // Which phases touch the tile (or feed this lane's motion gradient);
-            // all their upstream-gradient loads are issued together.
-            bool any[KT], mine[KT];
-            float g[KT][CT];
+            for (int ch = 0; ch < CT; ++ch) d.g[k][ch] = *at(gframe + (k * CT + ch) * hw, pc);
+    };
+
+    SegLoad<T, CT, KT> cur, nxt;
+    int code = next_seg();
+    if (code >= 0) load_seg(code, cur);
+    while (code >= 0) {
+        const int ncode = next_seg();
+        if (ncode >= 0) load_seg(ncode, nxt);
+
+        const int i = code >> 1;  // wave-uniform
+        const bool near = code & 1;
+        const int y = r_lo + i / nsc;
+        const int sx0 = (sc_lo + i % nsc) * kSegW;
+        const int x = sx0 + lane;
+        const bool inx = x < w;
+        PTaps t[KT];
+        float g[KT][CT];
 #pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                const bool inx0 = (unsigned)(t[k].ax.i0 - tx0) < (unsigned)kTileW;
-                const bool inx1 = (unsigned)(t[k].ax.i1 - tx0) < (unsigned)kTileW;
-                const bool iny0 = (unsigned)(t[k].ay.i0 - ty0) < (unsigned)TH;
-                const bool iny1 = (unsigned)(t[k].ay.i1 - ty0) < (unsigned)TH;
-                any[k] = t[k].valid && (inx0 || inx1) && (iny0 || iny1);
-                mine[k] = owner && t[k].valid;
-                const T *gk = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw;
+        for (int k = 0; k < KT; ++k) {
+            t[k].ax = split_axis(a.s[k] * cur.u, x, w);
+            t[k].ay = split_axis(a.s[k] * cur.v, y, h);
+            t[k].valid = inx && t[k].ax.ok && t[k].ay.ok;
 #pragma unroll
-                for (int ch = 0; ch < CT; ++ch)
-                    g[k][ch] = (any[k] || mine[k]) ? to_f32(*at(gk + ch * hw, p)) : 0.0f;
-            }
-            if (owner) {
-                float gu = 0.0f, gv = 0.0f;
+            for (int ch = 0; ch < CT; ++ch) g[k][ch] = to_f32(cur.g[k][ch]);
+        }
+
+        // Motion gradient of the home segments (every pixel written once).
+        if (a.gmv && (unsigned)(y - ty0) < (unsigned)TH && sx0 / kTileW == tx) {
+            float gu = 0.0f, gv = 0.0f;
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    if (mine[k]) motion_grad_phase<T, CT>(img, hw, w, t[k], g[k], a.s[k], gu, gv);
+            for (int k = 0; k < KT; ++k)
+                if (t[k].valid) motion_grad_phase<T, CT>(img, hw, w, t[k], g[k], a.s[k], gu, gv);
+            if (inx) {
                 float *gm = a.gmv + 2 * static_cast<int64_t>(in) * hw;
+                const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + x;
                 *at(gm, p) = gu;
                 *at(gm + hw, p) = gv;
             }
+        }
+
+        if (near) {  // wave-uniform; far segments are scattered by pass 3
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                const unsigned long long any_m = __ballot(any[k]);
-                if (any_m == 0ull) continue;  // wave-uniform
                 const int lx0 = t[k].ax.i0 - tx0, lx1 = t[k].ax.i1 - tx0;
                 const int ly0 = t[k].ay.i0 - ty0, ly1 = t[k].ay.i1 - ty0;
                 const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
                 const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
                 const bool iny0 = (unsigned)ly0 < (unsigned)TH;
                 const bool iny1 = (unsigned)ly1 < (unsigned)TH;
+                const bool any = t[k].valid && (inx0 || inx1) && (iny0 || iny1);
+                const unsigned long long any_m = __ballot(any);
+                if (any_m == 0ull) continue;  // wave-uniform
                 // Uniform offset: that of the first lane with an in-tile tap.
                 const int offx = x - t[k].ax.i0, offy = y - t[k].ay.i0;
                 const int src_lane = __builtin_ctzll(any_m);
                 const int rx = __builtin_amdgcn_readlane(offx, src_lane);
                 const int ry = __builtin_amdgcn_readlane(offy, src_lane);
-                const bool uni = any[k] && offx == rx && offy == ry;
+                const bool uni = any && offx == rx && offy == ry;
                 const float fx = t[k].ax.f, fy = t[k].ay.f;
                 const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
                 const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
-                // Cells of the uniform pattern at this lane; lanes whose cell is
-                // outside the tile read and write a dummy word (adding 0), so the
-                // read-add-writes need no branches and can be batched.
                 const int ux = x - rx - tx0;
-                const int uy0 = y - ry - ty0, uy1 = uy0 + 1;
+                const int uy0 = y - ry - ty0;
                 const bool cx = (unsigned)ux < (unsigned)kTileW;
-                const bool cx1 = lane == kSegW - 1 && (unsigned)(ux + 1) < (unsigned)kTileW;
-                const bool cy0 = (unsigned)uy0 < (unsigned)TH;
-                const bool cy1 = (unsigned)uy1 < (unsigned)TH;
-                const int plane_sz = TH * kTileW;
-                const int dummy = CT * plane_sz;
-                const int i_top = cx && cy0 ? uy0 * kTileW + ux : dummy;
-                const int i_bot = cx && cy1 ? uy1 * kTileW + ux : dummy;
-                const int i_et = cx1 && cy0 ? uy0 * kTileW + ux + 1 : dummy;
-                const int i_eb = cx1 && cy1 ? uy1 * kTileW + ux + 1 : dummy;
-                float c01[CT], c11[CT], top[CT], bot[CT];
+                const int scratch = ncells + lane;
+                const int c_top = cx && (unsigned)uy0 < (unsigned)TH ? uy0 * kTileW + ux : scratch;
+                const int c_bot =
+                    cx && (unsigned)(uy0 + 1) < (unsigned)TH ? (uy0 + 1) * kTileW + ux : scratch;
+                float c01[CP], c11[CP], rt[CP], rb[CP];
+                cell_read<CP>(acc, c_top, rt);
+                cell_read<CP>(acc, c_bot, rb);
+                // (lanes off the pattern take part with g = 0: their cell of
+                // the pattern still receives the left neighbour's taps)
 #pragma unroll
                 for (int ch = 0; ch < CT; ++ch) {
                     const float gg = uni ? g[k][ch] : 0.0f;
                     c01[ch] = w01 * gg;
                     c11[ch] = w11 * gg;
-                    top[ch] = fmaf(w00, gg, shift_up1(c01[ch]));
-                    bot[ch] = fmaf(w10, gg, shift_up1(c11[ch]));
+                    rt[ch] += fmaf(w00, gg, shift_up1(c01[ch]));
+                    rb[ch] += fmaf(w10, gg, shift_up1(c11[ch]));
                 }
-                // Dummy indices stay at the single dummy word for every channel.
-#define EXW_CELL(i, ch) ((i) == dummy ? dummy : (ch) * plane_sz + (i))
-                float rt[CT], rb[CT];
+                cell_write<CP>(acc, c_top, rt);
+                cell_write<CP>(acc, c_bot, rb);
+                // lane 63's right-hand taps, one cell to the right
+                if (lane == kSegW - 1 && (unsigned)(ux + 1) < (unsigned)kTileW) {
+                    if ((unsigned)uy0 < (unsigned)TH) {
+                        const int c = uy0 * kTileW + ux + 1;
+                        cell_read<CP>(acc, c, rt);
 #pragma unroll
-                for (int ch = 0; ch < CT; ++ch) {
-                    rt[ch] = acc[EXW_CELL(i_top, ch)];
-                    rb[ch] = acc[EXW_CELL(i_bot, ch)];
-                }
-#pragma unroll
-                for (int ch = 0; ch < CT; ++ch) {
-                    acc[EXW_CELL(i_top, ch)] = rt[ch] + (cx && cy0 ? top[ch] : 0.0f);
-                    acc[EXW_CELL(i_bot, ch)] = rb[ch] + (cx && cy1 ? bot[ch] : 0.0f);
-                }
-                if (__ballot(cx1 && (cy0 || cy1))) {  // lane 63's right-hand taps
-#pragma unroll
-                    for (int ch = 0; ch < CT; ++ch) {
-                        rt[ch] = acc[EXW_CELL(i_et, ch)];
-                        rb[ch] = acc[EXW_CELL(i_eb, ch)];
+                        for (int ch = 0; ch < CT; ++ch) rt[ch] += c01[ch];
+                        cell_write<CP>(acc, c, rt);
                     }
+                    if ((unsigned)(uy0 + 1) < (unsigned)TH) {
+                        const int c = (uy0 + 1) * kTileW + ux + 1;
+                        cell_read<CP>(acc, c, rb);
 #pragma unroll
-                    for (int ch = 0; ch < CT; ++ch) {
-                        acc[EXW_CELL(i_et, ch)] = rt[ch] + (cx1 && cy0 ? c01[ch] : 0.0f);
-                        acc[EXW_CELL(i_eb, ch)] = rb[ch] + (cx1 && cy1 ? c11[ch] : 0.0f);
+                        for (int ch = 0; ch < CT; ++ch) rb[ch] += c11[ch];
+                        cell_write<CP>(acc, c, rb);
                     }
                 }
-#undef EXW_CELL
                 // Lanes off the uniform pattern (motion boundaries): LDS atomics.
-                if (__ballot(any[k] && !uni)) {
-                    if (any[k] && !uni) {
+                if (__ballot(any && !uni)) {
+                    if (any && !uni) {
 #pragma unroll
                         for (int ch = 0; ch < CT; ++ch) {
-                            float *pl = acc + ch * plane_sz;
-                            if (inx0 && iny0 && w00 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx0, w00 * g[k][ch]);
-                            if (inx1 && iny0 && w01 != 0.0f) atomicAdd(pl + ly0 * kTileW + lx1, w01 * g[k][ch]);
-                            if (inx0 && iny1 && w10 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx0, w10 * g[k][ch]);
-                            if (inx1 && iny1 && w11 != 0.0f) atomicAdd(pl + ly1 * kTileW + lx1, w11 * g[k][ch]);
+                            const float gg = g[k][ch];
+                            if (inx0 && iny0 && w00 != 0.0f)
+                                atomicAdd(acc + (ly0 * kTileW + lx0) * CP + ch, w00 * gg);
+                            if (inx1 && iny0 && w01 != 0.0f)
+                                atomicAdd(acc + (ly0 * kTileW + lx1) * CP + ch, w01 * gg);
+                            if (inx0 && iny1 && w10 != 0.0f)
+                                atomicAdd(acc + (ly1 * kTileW + lx0) * CP + ch, w10 * gg);
+                            if (inx1 && iny1 && w11 != 0.0f)
+                                atomicAdd(acc + (ly1 * kTileW + lx1) * CP + ch, w11 * gg);
                         }
                     }
                 }
             }
         }
+        code = ncode;
+        cur = nxt;
     }
 
     if (!a.gsrc) return;
-    // Store the finished tile. 16-bit frames that also receive far-segment
-    // atomics go through the float32 accumulator instead.
+    // Store the finished tile, one pixel (all channels) per lane and step. 16-bit
+    // frames that also receive far-segment atomics go through the float32
+    // accumulator instead.
     const bool to_accum = fi.has_far && a.accum32 != nullptr;
-    for (int i = lane; i < C * TH * kTileW; i += kSegW) {
-        const int ch = i / (TH * kTileW);
-        const int rem = i % (TH * kTileW);
-        const int X = tx0 + rem % kTileW, Y = ty0 + rem / kTileW;
+    for (int c = lane; c < ncells; c += kSegW) {
+        const int X = tx0 + c % kTileW, Y = ty0 + c / kTileW;
         if (X >= w || Y >= h) continue;
-        const int64_t plane = (static_cast<int64_t>(in) * C + ch) * hw;
+        float v[CP];
+        cell_read<CP>(acc, c, v);
         const uint32_t o = static_cast<uint32_t>(Y) * static_cast<uint32_t>(w) + X;
-        if (to_accum)
-            *at(a.accum32 + plane, o) = acc[i];
-        else
-            *at(a.gsrc + plane, o) = from_f32<T>(acc[i]);
+        const int64_t frame = static_cast<int64_t>(in) * CT * hw;
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) {
+            if (to_accum)
+                *at(a.accum32 + frame + ch * hw, o) = v[ch];
+            else
+                *at(a.gsrc + frame + ch * hw, o) = from_f32<T>(v[ch]);
+        }
     }
 }
 
 // ---------------------------------------------------------------- pass 3
 
-// Far segments: scatter with global float32 atomics, motion gradient per pixel.
+// Far segments: scatter with global float32 atomics (their motion gradient is
+// computed by their home tile in pass 2).
 template <typename T, int CT, int KT>
 __global__ __launch_bounds__(kThreads) void adjoint_far_kernel(BwdArgs<T> a, float *accum) {
     const int C = CT, w = a.w, h = a.h;
@@ -435,8 +507,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_far_kernel(BwdArgs<T> a, flo
     const int64_t per_frame = static_cast<int64_t>(h) * a.segs;
     for (int in = 0; in < a.n; ++in) {
         if (!a.info[in].has_far) continue;  // uniform across the grid
-        const T *img = a.src ? a.src + static_cast<int64_t>(in) * C * hw : nullptr;
-        float *acc = accum ? accum + static_cast<int64_t>(in) * C * hw : nullptr;
+        float *acc = accum + static_cast<int64_t>(in) * C * hw;
         for (int64_t sg = static_cast<int64_t>(blockIdx.x) * (kThreads / kSegW) + wave;
              sg < per_frame; sg += static_cast<int64_t>(gridDim.x) * (kThreads / kSegW)) {
             const int y = static_cast<int>(sg / a.segs);
@@ -448,39 +519,26 @@ __global__ __launch_bounds__(kThreads) void adjoint_far_kernel(BwdArgs<T> a, flo
             const int64_t p = static_cast<int64_t>(y) * w + x;
             const float u = a.mv[(2 * static_cast<int64_t>(in)) * hw + p];
             const float v = a.mv[(2 * static_cast<int64_t>(in) + 1) * hw + p];
-            float gu = 0.0f, gv = 0.0f;
-            bool any = false;
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                PTaps t;
-                t.ax = split_axis(a.s[k] * u, x, w);
-                t.ay = split_axis(a.s[k] * v, y, h);
-                if (!(t.ax.ok && t.ay.ok)) continue;
-                any = true;
+                const Axis ax = split_axis(a.s[k] * u, x, w);
+                const Axis ay = split_axis(a.s[k] * v, y, h);
+                if (!(ax.ok && ay.ok)) continue;
                 const T *gp = a.gout + (static_cast<int64_t>(in) * KT + k) * C * hw + p;
-                float g[CT];
+                const float fx = ax.f, fy = ay.f;
+                const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+                const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+                const int64_t r0 = static_cast<int64_t>(ay.i0) * w;
+                const int64_t r1 = static_cast<int64_t>(ay.i1) * w;
 #pragma unroll
-                for (int ch = 0; ch < CT; ++ch) g[ch] = to_f32(gp[ch * hw]);
-                if (acc) {
-                    const float fx = t.ax.f, fy = t.ay.f;
-                    const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
-                    const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
-                    const int64_t r0 = static_cast<int64_t>(t.ay.i0) * w;
-                    const int64_t r1 = static_cast<int64_t>(t.ay.i1) * w;
-#pragma unroll
-                    for (int ch = 0; ch < CT; ++ch) {
-                        float *pl = acc + ch * hw;
-                        if (w00 != 0.0f) atomicAdd(pl + r0 + t.ax.i0, w00 * g[ch]);
-                        if (w01 != 0.0f) atomicAdd(pl + r0 + t.ax.i1, w01 * g[ch]);
-                        if (w10 != 0.0f) atomicAdd(pl + r1 + t.ax.i0, w10 * g[ch]);
-                        if (w11 != 0.0f) atomicAdd(pl + r1 + t.ax.i1, w11 * g[ch]);
-                    }
+                for (int ch = 0; ch < CT; ++ch) {
+                    const float g = to_f32(gp[ch * hw]);
+                    float *pl = acc + ch * hw;
+                    if (w00 != 0.0f) atomicAdd(pl + r0 + ax.i0, w00 * g);
+                    if (w01 != 0.0f) atomicAdd(pl + r0 + ax.i1, w01 * g);
+                    if (w10 != 0.0f) atomicAdd(pl + r1 + ax.i0, w10 * g);
+                    if (w11 != 0.0f) atomicAdd(pl + r1 + ax.i1, w11 * g);
                 }
-                if (a.gmv) motion_grad_phase<T, CT>(img, hw, w, t, g, a.s[k], gu, gv);
-            }
-            if (a.gmv && any) {
-                a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
-                a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;
             }
         }
     }
@@ -664,10 +722,11 @@ hipError_t run(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
     const unsigned foot_blocks =
         static_cast<unsigned>((foot_units + kThreads / kSegW - 1) / (kThreads / kSegW));
     hipLaunchKernelGGL((footprint_kernel<KT>), dim3(foot_blocks), dim3(kThreads), 0, st, a.mv,
-                       a.gmv, a.boxes, a.info, a.n, a.h, a.w, a.segs, ph);
+                       a.boxes, a.info, a.n, a.h, a.w, a.segs, ph);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    const size_t lds = sizeof(float) * (CT * a.tile_h * kTileW + 1);  // + dummy word
+    // cells of the tile plus one scratch cell per lane
+    const size_t lds = sizeof(float) * CellWidth<CT>::value * (a.tile_h * kTileW + kSegW);
     const int64_t tiles = static_cast<int64_t>(a.n) * a.tiles_x * a.tiles_y;
     hipLaunchKernelGGL((adjoint_tiles_kernel<T, CT, KT>), dim3(static_cast<unsigned>(tiles)),
                        dim3(kSegW), lds, st, a);
