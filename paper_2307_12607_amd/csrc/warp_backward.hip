@@ -159,7 +159,7 @@ struct PTaps {
 };
 
 template <typename T, int CT>
-__device__ __forceinline__ void motion_grad_phase(const T *img, int64_t hw, int w, const PTaps &t,
+__device__ __forceinline__ void motion_grad_phase(const T *const *iplane, int w, const PTaps &t,
                                                   const float *g, float s, float &gu, float &gv) {
     const int xl = min(t.ax.i0, w - 2);
     const bool last = t.ax.i0 == w - 1;
@@ -169,7 +169,7 @@ __device__ __forceinline__ void motion_grad_phase(const T *img, int64_t hw, int 
     float su = 0.0f, sv = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < CT; ++ch) {
-        const T *pl = img + ch * hw;
+        const T *pl = iplane[ch];
         float a0, b0, a1, b1;
         if (w >= 2) {
             load_pair(at(pl, o0), a0, b0);
@@ -190,9 +190,10 @@ __device__ __forceinline__ void motion_grad_phase(const T *img, int64_t hw, int 
     gv = fmaf(-s, sv, gv);
 }
 
-// v from lane - 1 (0 into lane 0): a DPP wavefront shift.
+// v from lane - 1 (0 into lane 0): a DPP wavefront shift whose out-of-range
+// source reads as zero, so it folds into the consuming add.
 __device__ __forceinline__ float shift_up1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 // Channels of one LDS cell: padded to a multiple of four (one 16-byte LDS
@@ -338,6 +339,16 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         m_hit &= m_hit - 1;
         return ((base - kSegW + j) << 1) | static_cast<int>((m_near >> j) & 1ull);
     };
+    // Plane base pointers, loop-invariant and wave-uniform (scalar registers);
+    // each load adds a 32-bit in-plane offset.
+    const T *gplane[KT][CT];
+    const T *iplane[CT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) gplane[k][ch] = gframe + (k * CT + ch) * hw;
+#pragma unroll
+    for (int ch = 0; ch < CT; ++ch) iplane[ch] = img ? img + ch * hw : nullptr;
     auto load_seg = [&](int code, SegLoad<T, CT, KT> &d) {
         const int i = code >> 1;
         const int y = r_lo + i / nsc;
@@ -349,7 +360,7 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < KT; ++k)
 #pragma unroll
-            for (int ch = 0; ch < CT; ++ch) d.g[k][ch] = *at(gframe + (k * CT + ch) * hw, pc);
+            for (int ch = 0; ch < CT; ++ch) d.g[k][ch] = *at(gplane[k][ch], pc);
     };
 
     SegLoad<T, CT, KT> cur, nxt;
@@ -381,7 +392,7 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
             float gu = 0.0f, gv = 0.0f;
 #pragma unroll
             for (int k = 0; k < KT; ++k)
-                if (t[k].valid) motion_grad_phase<T, CT>(img, hw, w, t[k], g[k], a.s[k], gu, gv);
+                if (t[k].valid) motion_grad_phase<T, CT>(iplane, w, t[k], g[k], a.s[k], gu, gv);
             if (inx) {
                 float *gm = a.gmv + 2 * static_cast<int64_t>(in) * hw;
                 const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + x;
@@ -428,8 +439,8 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                     const float gg = uni ? g[k][ch] : 0.0f;
                     c01[ch] = w01 * gg;
                     c11[ch] = w11 * gg;
-                    rt[ch] += fmaf(w00, gg, shift_up1(c01[ch]));
-                    rb[ch] += fmaf(w10, gg, shift_up1(c11[ch]));
+                    rt[ch] = fmaf(w00, gg, rt[ch]) + shift_up1(c01[ch]);
+                    rb[ch] = fmaf(w10, gg, rb[ch]) + shift_up1(c11[ch]);
                 }
                 cell_write<CP>(acc, c_top, rt);
                 cell_write<CP>(acc, c_bot, rb);
@@ -577,6 +588,9 @@ __global__ __launch_bounds__(kThreads) void motion_grad_kernel(BwdArgs<T> a) {
     const int64_t hw = static_cast<int64_t>(h) * w;
     const int64_t p = static_cast<int64_t>(y) * w + x;
     const T *img = a.src + static_cast<int64_t>(in) * CT * hw;
+    const T *iplane[CT];
+#pragma unroll
+    for (int ch = 0; ch < CT; ++ch) iplane[ch] = img + ch * hw;
     const float u = a.mv[(2 * static_cast<int64_t>(in)) * hw + p];
     const float v = a.mv[(2 * static_cast<int64_t>(in) + 1) * hw + p];
     float gu = 0.0f, gv = 0.0f;
@@ -590,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void motion_grad_kernel(BwdArgs<T> a) {
         float g[CT];
 #pragma unroll
         for (int ch = 0; ch < CT; ++ch) g[ch] = to_f32(gp[ch * hw]);
-        motion_grad_phase<T, CT>(img, hw, w, t, g, a.s[k], gu, gv);
+        motion_grad_phase<T, CT>(iplane, w, t, g, a.s[k], gu, gv);
     }
     a.gmv[(2 * static_cast<int64_t>(in)) * hw + p] = gu;
     a.gmv[(2 * static_cast<int64_t>(in) + 1) * hw + p] = gv;

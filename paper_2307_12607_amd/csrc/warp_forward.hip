@@ -81,15 +81,28 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
         u = *at(mu, p);
         v = *at(mu + hw, p);
     }
+    // Plane base pointers: loop-invariant and wave-uniform (scalar registers),
+    // so every access is a scalar base plus a 32-bit vector offset.
     const T *img = a.src + static_cast<int64_t>(q.in) * CT * hw;
+    const T *iplane[CT];
+    T *oplane[KT][CT];
+    uint8_t *mplane[KT];
+#pragma unroll
+    for (int ch = 0; ch < CT; ++ch) iplane[ch] = img + ch * hw;
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        const int64_t plane = static_cast<int64_t>(q.in) * KT + j;
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) oplane[j][ch] = a.out + (plane * CT + ch) * hw;
+        mplane[j] = a.mask ? a.mask + plane * hw : nullptr;
+    }
 #pragma unroll 1
     for (int j = 0; j < KT; ++j) {
-        // phase j without dynamic indexing of the argument array
+        // phase j without dynamic indexing of the argument arrays
         const float sj = j == 0 ? a.s[0] : (j == 1 ? a.s[1] : (j == 2 ? a.s[2] : a.s[3]));
         const Axis ax = split_axis(sj * u, q.x, w);
         const Axis ay = split_axis(sj * v, q.y, h);
         const bool valid = q.inside && ax.ok && ay.ok;
-        const int64_t plane = static_cast<int64_t>(q.in) * KT + j;
         if (q.inside) {
             const float w00 = (1.0f - ax.f) * (1.0f - ay.f);
             const float w01 = ax.f * (1.0f - ay.f);
@@ -104,11 +117,10 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
             float vals[CT];
 #pragma unroll
             for (int ch = 0; ch < CT; ++ch) {
-                const T *pl = img + ch * hw;
                 float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
                 if (valid) {
-                    load_pair(at(pl, o0), a0, b0);
-                    load_pair(at(pl, o1), a1, b1);
+                    load_pair(at(iplane[ch], o0), a0, b0);
+                    load_pair(at(iplane[ch], o1), a1, b1);
                 }
                 float acc = w00 * (last ? b0 : a0);
                 acc = fmaf(w01, b0, acc);
@@ -116,12 +128,16 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
                 acc = fmaf(w11, b1, acc);
                 vals[ch] = valid ? acc : 0.0f;
             }
-            T *o = a.out + plane * CT * hw;
+            T *const *op = oplane[0];
+            uint8_t *mp = mplane[0];
 #pragma unroll
-            for (int ch = 0; ch < CT; ++ch) *at(o + ch * hw, p) = from_f32<T>(vals[ch]);
-            if (a.mask) *at(a.mask + plane * hw, p) = valid ? 1 : 0;
+            for (int jj = 1; jj < KT; ++jj)
+                if (j == jj) { op = oplane[jj]; mp = mplane[jj]; }
+#pragma unroll
+            for (int ch = 0; ch < CT; ++ch) *at(op[ch], p) = from_f32<T>(vals[ch]);
+            if (mp) *at(mp, p) = valid ? 1 : 0;
         }
-        if (a.count) count_invalid(a.count, plane, q.inside, valid);
+        if (a.count) count_invalid(a.count, static_cast<int64_t>(q.in) * KT + j, q.inside, valid);
     }
 }
 
