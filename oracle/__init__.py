@@ -7,6 +7,8 @@ path never does, and shares no code with it.
 
 * ``warp_oracle``: vectorised NumPy over pixels, following the definition in
   the order the method states it.
+* ``scene_stats``: the per-frame motion mean and variance and the other
+  scene-state quantities that accompany a warp.
 * ``warp_ref.c`` (+ ``ref_c``): the same definition as scalar C loops in
   float64, built with gcc (no HIP); used for the cross-check and as the timed
   CPU baseline.
