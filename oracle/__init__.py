@@ -9,6 +9,8 @@ path never does, and shares no code with it.
   the order the method states it.
 * ``scene_stats``: the per-frame motion mean and variance and the other
   scene-state quantities that accompany a warp.
+* ``quality``: per-frame MSE, PSNR and SSIM of a predicted frame against
+  the ground truth.
 * ``warp_ref.c`` (+ ``ref_c``): the same definition as scalar C loops in
   float64, built with gcc (no HIP); used for the cross-check and as the timed
   CPU baseline.
