@@ -161,6 +161,29 @@ class Workload:
             "bwd_gbs": self.bwd_bytes / (bwd_ms * 1e-3) / 1e9,
         }
 
+    def run_motion_stats(self, reps=20):
+        """Per-frame motion mean/variance (one read of the motion planes)."""
+        import paper_2307_12607_amd as exw
+        torch = self.torch
+        n, c, h, w, k = self.shape
+        nb = exw.exw_motion_stats_workspace_bytes(n, h, w)
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.sets[0]["mv"].device)
+        out = torch.empty((n, 4), dtype=torch.float64, device=ws.device)
+        for i in range(3):
+            exw.exw_motion_stats(self.sets[i % len(self.sets)]["mv"], out, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            exw.exw_motion_stats(self.sets[i % len(self.sets)]["mv"], out, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        gbs = 8 * n * h * w / (us * 1e-6) / 1e9
+        return {"workload": f"config{self.spec.index}: motion statistics of {n}x{w}x{h}",
+                "us": round(us, 2), "alg_bytes": 8 * n * h * w, "gbs": round(gbs, 1),
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
     def free(self):
         self.sets = []
         self.torch.cuda.empty_cache()
@@ -243,6 +266,7 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     wl_name = main_wl.name()
     traffic = load_traffic(dominant, wl_name)
+    stats_line = main_wl.run_motion_stats()
     main_wl.free()
 
     variants = []
@@ -289,6 +313,7 @@ def main():
                       "fwd_alg_bytes": main_wl.fwd_bytes, "bwd_alg_bytes": main_wl.bwd_bytes,
                       "copy_ceiling_gbs": round(ceiling, 1)},
         "variants": variants,
+        "motion_stats": stats_line,
     }
     print(json.dumps(rec), flush=True)
 

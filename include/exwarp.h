@@ -154,6 +154,80 @@ exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_
                              float *grad_mv, void *workspace, size_t workspace_bytes,
                              void *stream);
 
+/* ------------------------------------------------------------------------
+ * Scene-state statistics that accompany a warp.
+ *
+ * Paper §V: the state the warp/extrapolate decision is taken on includes the
+ * variance of the motion-vector buffer, horizontally and vertically
+ * (Var_x(F_mv), Var_y(F_mv) in the environment vector E_t; Table IV lists the
+ * motion variance as the feature that reveals dynamic objects). Here it is
+ * the population variance over all H*W per-pixel vectors of a frame.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace exw_motion_stats needs for N frames of H x W:
+ * 48 bytes per workgroup partial, at most 128 partials per frame. Returns 0
+ * for an empty batch. */
+size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w);
+
+/*
+ * Per-frame motion statistics:
+ *   stats[n][0] = mean of mv[n, 0]   stats[n][1] = population variance of mv[n, 0]
+ *   stats[n][2] = mean of mv[n, 1]   stats[n][3] = population variance of mv[n, 1]
+ * in float64, over all H*W values of each plane.
+ *   mv:        [N, 2, H, W] float32, device, 4-byte aligned.
+ *   stats:     [N, 4] float64, device, 8-byte aligned; overwritten.
+ *   workspace: device scratch of at least exw_motion_stats_workspace_bytes()
+ *              bytes, 256-byte aligned.
+ * Each frame is read once; per-thread chunks, lanes, wavefronts and
+ * workgroups are combined with the pairwise (count, mean, sum of squared
+ * deviations) update in float64, in a fixed order: the result is
+ * reproducible bit for bit and does not cancel when the mean is large
+ * against the spread. A non-finite value makes its component's mean and
+ * variance non-finite. N = 0 does nothing; N > 0 with H = 0 or W = 0 is
+ * EXW_ERROR_INVALID_VALUE (an empty frame has no variance); N >= 2^23 or
+ * H*W > 2^30 is EXW_ERROR_UNSUPPORTED.
+ */
+exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Frame quality.
+ *
+ * Paper §V: the reward of the warp/extrapolate decision is the gain in PSNR
+ * (10 log10(peak^2 / MSE)) and in SSIM of the frame an action produces over
+ * the frame the other action would have produced, both against the ground
+ * truth.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace exw_frame_quality needs: 16 bytes per strip of
+ * 64 x 66 SSIM positions of each channel of each frame. Returns 0 for an
+ * empty batch or frames below 11 x 11. */
+size_t exw_frame_quality_workspace_bytes(int32_t b, int32_t c, int32_t h, int32_t w);
+
+/*
+ * Per-frame quality of B predicted frames against B ground-truth frames:
+ *   quality[b][0] = MSE  = mean over C*H*W of (pred - truth)^2
+ *   quality[b][1] = PSNR = 10 log10(peak^2 / MSE)  (+inf when MSE = 0)
+ *   quality[b][2] = SSIM = mean over channels and over the (H-10)*(W-10)
+ *                   positions where the window fits, of the index of Wang et
+ *                   al. (2004): 11 x 11 Gaussian window, standard deviation
+ *                   1.5, normalised; C1 = (0.01 peak)^2, C2 = (0.03 peak)^2.
+ *   pred, truth: [B, C, H, W] in `dtype` (any leading batch shape flattened
+ *                into B, e.g. the [N, K, C, H, W] output of a warp), device,
+ *                aligned to the element size.
+ *   quality:     [B, 3] float64, device, 8-byte aligned; overwritten.
+ *   workspace:   device scratch of at least exw_frame_quality_workspace_bytes()
+ *                bytes, 256-byte aligned.
+ *   peak:        the value range of the frames (1.0 for unit-range frames;
+ *                the paper's 255 for 8-bit frames), finite and > 0.
+ * All window sums, the SSIM index and the sums are float64; the order of
+ * every sum is fixed, so results are reproducible bit for bit. B = 0 does
+ * nothing; H or W below 11 is EXW_ERROR_INVALID_VALUE.
+ */
+exw_status exw_frame_quality(const void *pred, const void *truth, exw_dtype dtype, int32_t b,
+                             int32_t c, int32_t h, int32_t w, double peak, double *quality,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

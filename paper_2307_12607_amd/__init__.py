@@ -10,6 +10,10 @@ package marshals torch tensors to that ABI:
 * ``warp``: allocate outputs and run the batched forward warp.
 * ``WarpFunction`` / ``warp_differentiable``: autograd over the hand-written
   adjoint (gradients for the frames and the motion vectors).
+* ``motion_stats``: per-frame mean and variance of the motion field, the
+  scene-state feature the warp/extrapolate decision is taken on (§V).
+* ``frame_quality``: per-frame MSE, PSNR and SSIM against the ground truth,
+  the quality terms of the decision's reward (§V).
 """
 
 from __future__ import annotations
@@ -23,6 +27,10 @@ from .binding import (  # noqa: F401
     exw_warp_backward,
     exw_warp_backward_batched,
     exw_warp_backward_workspace_bytes,
+    exw_frame_quality,
+    exw_frame_quality_workspace_bytes,
+    exw_motion_stats,
+    exw_motion_stats_workspace_bytes,
     exw_warp_forward,
     exw_warp_forward_batched,
 )
@@ -101,6 +109,36 @@ def warp_differentiable(src, mv, phases=(1.0,)):
     return WarpFunction.apply(src, mv, tuple(phases))
 
 
+def motion_stats(mv: torch.Tensor) -> torch.Tensor:
+    """Per-frame ``(mean_x, var_x, mean_y, var_y)`` of ``mv`` [N,2,H,W] as a
+    float64 [N,4] device tensor (population variance over all pixels)."""
+    mv = mv.contiguous()
+    n, _, h, w = mv.shape
+    stats = torch.empty((n, 4), dtype=torch.float64, device=mv.device)
+    nbytes = exw_motion_stats_workspace_bytes(n, h, w)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=mv.device)
+    exw_motion_stats(mv, stats, ws)
+    return stats
+
+
+def frame_quality(pred: torch.Tensor, truth: torch.Tensor, peak: float = 1.0) -> torch.Tensor:
+    """Per-frame ``(MSE, PSNR, SSIM)`` of ``pred`` against ``truth``, both
+    [..., C, H, W] of one dtype, as a float64 [..., 3] device tensor."""
+    if pred.shape != truth.shape or pred.dim() < 3:
+        raise ValueError("pred and truth must both be [..., C, H, W] of one shape")
+    lead = pred.shape[:-3]
+    c, h, w = pred.shape[-3:]
+    p = pred.contiguous().reshape(-1, c, h, w)
+    t = truth.contiguous().reshape(-1, c, h, w)
+    q = torch.empty((p.shape[0], 3), dtype=torch.float64, device=pred.device)
+    nbytes = exw_frame_quality_workspace_bytes(p.shape[0], c, h, w)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=pred.device)
+    exw_frame_quality(p, t, q, ws, peak)
+    return q.reshape(*lead, 3)
+
+
 __all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differentiable",
-           "exw_warp_forward", "exw_warp_forward_batched", "exw_warp_backward",
-           "exw_warp_backward_batched", "exw_warp_backward_workspace_bytes"]
+           "motion_stats", "frame_quality", "exw_warp_forward", "exw_warp_forward_batched", "exw_warp_backward",
+           "exw_warp_backward_batched", "exw_warp_backward_workspace_bytes", "exw_motion_stats",
+           "exw_motion_stats_workspace_bytes", "exw_frame_quality",
+           "exw_frame_quality_workspace_bytes"]

@@ -153,6 +153,58 @@ def exw_warp_backward(src: Optional[torch.Tensor], mv: torch.Tensor, phase: floa
     check(st, "exw_warp_backward")
 
 
+def exw_motion_stats_workspace_bytes(n: int, h: int, w: int) -> int:
+    return int(lib().exw_motion_stats_workspace_bytes(n, h, w))
+
+
+def exw_motion_stats(mv: torch.Tensor, stats: torch.Tensor,
+                     workspace: Optional[torch.Tensor] = None, stream=None) -> None:
+    """mv [N,2,H,W] f32 -> stats [N,4] f64 = (mean_x, var_x, mean_y, var_y).
+    ``workspace``: a byte tensor of at least ``exw_motion_stats_workspace_bytes``."""
+    dev = mv.device
+    _dev(mv, "mv", dev)
+    if mv.dim() != 4 or mv.shape[1] != 2:
+        raise ValueError(f"mv has shape {tuple(mv.shape)}, expected [N, 2, H, W]")
+    if mv.dtype != torch.float32:
+        raise ValueError(f"mv has dtype {mv.dtype}, expected torch.float32")
+    n, _, h, w = mv.shape
+    _expect(stats, "stats", (n, 4), torch.float64, dev)
+    ws_bytes = 0
+    if workspace is not None:
+        _dev(workspace, "workspace", dev)
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib().exw_motion_stats(_ptr(mv), n, h, w, _ptr(stats), _ptr(workspace), ws_bytes,
+                                _stream(dev, stream))
+    check(st, "exw_motion_stats")
+
+
+def exw_frame_quality_workspace_bytes(b: int, c: int, h: int, w: int) -> int:
+    return int(lib().exw_frame_quality_workspace_bytes(b, c, h, w))
+
+
+def exw_frame_quality(pred: torch.Tensor, truth: torch.Tensor, quality: torch.Tensor,
+                      workspace: Optional[torch.Tensor] = None, peak: float = 1.0,
+                      stream=None) -> None:
+    """pred, truth [B,C,H,W] (same dtype) -> quality [B,3] f64 = (MSE, PSNR, SSIM).
+    ``workspace``: a byte tensor of at least ``exw_frame_quality_workspace_bytes``."""
+    dev = pred.device
+    _dev(pred, "pred", dev)
+    if pred.dim() != 4:
+        raise ValueError(f"pred has shape {tuple(pred.shape)}, expected [B, C, H, W]")
+    b, c, h, w = pred.shape
+    _expect(truth, "truth", (b, c, h, w), pred.dtype, dev)
+    _expect(quality, "quality", (b, 3), torch.float64, dev)
+    ws_bytes = 0
+    if workspace is not None:
+        _dev(workspace, "workspace", dev)
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib().exw_frame_quality(_ptr(pred), _ptr(truth), exw_dtype(pred.dtype), b, c, h, w,
+                                 ctypes.c_double(peak), _ptr(quality), _ptr(workspace), ws_bytes,
+                                 _stream(dev, stream))
+    check(st, "exw_frame_quality")
+
+
 __all__ = ["ExwError", "exw_dtype", "exw_warp_forward_batched", "exw_warp_forward",
            "exw_warp_backward_workspace_bytes", "exw_warp_backward_batched", "exw_warp_backward",
-           "_capi"]
+           "exw_motion_stats_workspace_bytes", "exw_motion_stats",
+           "exw_frame_quality_workspace_bytes", "exw_frame_quality", "_capi"]

@@ -269,4 +269,88 @@ exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_
                                      grad_mv, workspace, workspace_bytes, stream);
 }
 
+size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w) {
+    if (n <= 0 || h <= 0 || w <= 0) return 0;
+    return exw::motion_stats_workspace_bytes(n, h, w);
+}
+
+exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
+                            void *workspace, size_t workspace_bytes, void *stream) {
+    if (n < 0 || h < 0 || w < 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "negative size (n=%d, h=%d, w=%d)", n, h, w);
+    if (n > 0 && (h == 0 || w == 0))
+        return fail(EXW_ERROR_INVALID_VALUE, "empty frames have no statistics (h=%d, w=%d)", h,
+                    w);
+    if (n == 0) return succeed();
+    if (h >= (1 << 24) || w >= (1 << 24))
+        return fail(EXW_ERROR_UNSUPPORTED, "frame side >= 2^24 (h=%d, w=%d)", h, w);
+    const uint64_t hw = uint64_t(h) * uint64_t(w);
+    if (hw > (uint64_t(1) << 30))
+        return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu > 2^30", (unsigned long long)hw);
+    // the first pass runs at most 128 workgroups per frame in a 1-D grid
+    if (n >= (1 << 23)) return fail(EXW_ERROR_UNSUPPORTED, "frame count %d >= 2^23", n);
+    EXW_TRY(check_ptr("mv", mv, 4, true));
+    EXW_TRY(check_ptr("stats", stats, 8, true));
+    EXW_TRY(check_ptr("workspace", workspace, 256, true));
+    const size_t ws_need = exw::motion_stats_workspace_bytes(n, h, w);
+    if (workspace_bytes < ws_need)
+        return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
+                    workspace_bytes, ws_need);
+    const Span ins[] = {span("mv", mv, uint64_t(n) * 2u * hw * 4u)};
+    const Span outs[] = {span("stats", stats, uint64_t(n) * 4u * 8u),
+                         span("workspace", workspace, ws_need)};
+    EXW_TRY(check_disjoint(outs, 2, ins, 1));
+    return launched(exw::launch_motion_stats(mv, n, h, w, stats, workspace,
+                                             static_cast<hipStream_t>(stream)),
+                    "motion statistics launch");
+}
+
+size_t exw_frame_quality_workspace_bytes(int32_t b, int32_t c, int32_t h, int32_t w) {
+    if (b <= 0 || c <= 0 || h < 11 || w < 11) return 0;
+    return exw::quality_workspace_bytes(b, c, h, w);
+}
+
+exw_status exw_frame_quality(const void *pred, const void *truth, exw_dtype dtype, int32_t b,
+                             int32_t c, int32_t h, int32_t w, double peak, double *quality,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+    const size_t esize = dtype_size(dtype);
+    if (esize == 0) return fail(EXW_ERROR_INVALID_VALUE, "unknown dtype %d", int(dtype));
+    if (b < 0 || c < 0 || h < 0 || w < 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "negative size (b=%d, c=%d, h=%d, w=%d)", b, c, h, w);
+    if (!(std::isfinite(peak) && peak > 0.0))
+        return fail(EXW_ERROR_INVALID_VALUE, "peak must be finite and > 0");
+    if (b == 0) return succeed();
+    if (c < 1) return fail(EXW_ERROR_INVALID_VALUE, "channel count %d < 1", c);
+    if (h < 11 || w < 11)
+        return fail(EXW_ERROR_INVALID_VALUE,
+                    "frames smaller than the 11x11 SSIM window (h=%d, w=%d)", h, w);
+    if (h >= (1 << 24) || w >= (1 << 24))
+        return fail(EXW_ERROR_UNSUPPORTED, "frame side >= 2^24 (h=%d, w=%d)", h, w);
+    const uint64_t hw = uint64_t(h) * uint64_t(w);
+    const uint64_t elems = uint64_t(b) * uint64_t(c) * hw;
+    if (elems > kMaxElems)
+        return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu elements)",
+                    (unsigned long long)elems);
+    const uint64_t strips = uint64_t(b) * uint64_t(c) * ((uint64_t(w) - 10 + 63) / 64) *
+                            ((uint64_t(h) - 10 + 65) / 66);
+    if (strips >= (uint64_t(1) << 31))
+        return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu strips)",
+                    (unsigned long long)strips);
+    EXW_TRY(check_ptr("pred", pred, esize, true));
+    EXW_TRY(check_ptr("truth", truth, esize, true));
+    EXW_TRY(check_ptr("quality", quality, 8, true));
+    EXW_TRY(check_ptr("workspace", workspace, 256, true));
+    const size_t ws_need = exw::quality_workspace_bytes(b, c, h, w);
+    if (workspace_bytes < ws_need)
+        return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
+                    workspace_bytes, ws_need);
+    const Span ins[] = {span("pred", pred, elems * esize), span("truth", truth, elems * esize)};
+    const Span outs[] = {span("quality", quality, uint64_t(b) * 3u * 8u),
+                         span("workspace", workspace, ws_need)};
+    EXW_TRY(check_disjoint(outs, 2, ins, 2));
+    return launched(exw::launch_quality(dtype, pred, truth, b, c, h, w, peak, quality, workspace,
+                                        static_cast<hipStream_t>(stream)),
+                    "frame quality launch");
+}
+
 }  // extern "C"

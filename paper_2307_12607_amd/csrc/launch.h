@@ -38,4 +38,17 @@ hipError_t launch_backward(int dtype, const void *src, const float *mv, const Wa
                            const void *grad_out, void *grad_src, float *grad_mv,
                            const BwdWorkspace &ws, hipStream_t stream);
 
+// Per-frame mean and population variance of both motion components:
+// stats[n][4] = (mean_x, var_x, mean_y, var_y) in float64.
+size_t motion_stats_workspace_bytes(int n, int h, int w);
+hipError_t launch_motion_stats(const float *mv, int n, int h, int w, double *stats,
+                               void *workspace, hipStream_t stream);
+
+// Per-frame (MSE, PSNR, SSIM) of pred vs truth, both [B, C, H, W] in the
+// storage dtype, H, W >= 11: quality[b][3] in float64.
+size_t quality_workspace_bytes(int b, int c, int h, int w);
+hipError_t launch_quality(int dtype, const void *pred, const void *truth, int b, int c, int h,
+                          int w, double peak, double *quality, void *workspace,
+                          hipStream_t stream);
+
 }  // namespace exw

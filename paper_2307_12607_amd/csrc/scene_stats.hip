@@ -1,0 +1,149 @@
+// Per-frame motion statistics for CDNA4 (gfx950): mean and population
+// variance of the horizontal and the vertical motion component of every frame
+// (paper §V: the environment vector E_t holds Var_x(F_mv) and Var_y(F_mv);
+// Table IV: the motion variance is the feature that reveals dynamic objects).
+//
+// The motion planes are streamed once (8 bytes per pixel, HBM bound). Each
+// thread loads kChunk values per component with coalesced loads, forms the
+// chunk's mean and sum of squared deviations in float64 (two passes over
+// registers), and folds chunks, lanes, wavefronts and finally the partials
+// of all workgroups of a frame together with the pairwise update for
+// (count, mean, M2) (Chan, Golub and LeVeque). Every fold is in a fixed order,
+// so results are reproducible, and no step forms E[x^2] - E[x]^2, which
+// cancels when the mean is large against the spread.
+#include "launch.h"
+
+namespace exw {
+namespace {
+
+constexpr int kStatThreads = 256;
+constexpr int kChunk = 8;                          // values per thread, per component
+constexpr int kSpan = kStatThreads * kChunk;       // pixels per workgroup pass
+constexpr int kMaxParts = 128;                     // workgroups per frame, at most
+
+struct Moments {
+    double n, mean, m2;
+};
+
+__device__ __forceinline__ Moments fold(const Moments &a, const Moments &b) {
+    if (b.n == 0.0) return a;
+    if (a.n == 0.0) return b;
+    const double n = a.n + b.n;
+    const double d = b.mean - a.mean;
+    const double fb = b.n / n;
+    return Moments{n, a.mean + d * fb, a.m2 + b.m2 + d * d * a.n * fb};
+}
+
+__device__ __forceinline__ Moments shfl_xor(const Moments &m, int mask) {
+    return Moments{__shfl_xor(m.n, mask), __shfl_xor(m.mean, mask), __shfl_xor(m.m2, mask)};
+}
+
+// Fold over the 64 lanes of a wavefront (butterfly: every lane ends with the
+// same value, built in the same order).
+__device__ __forceinline__ Moments wave_fold(Moments m) {
+#pragma unroll
+    for (int mask = 1; mask < 64; mask <<= 1) {
+        const Moments o = shfl_xor(m, mask);
+        // lower lane of each pair first, so both lanes compute the same fold
+        m = (__lane_id() & mask) ? fold(o, m) : fold(m, o);
+    }
+    return m;
+}
+
+__device__ __forceinline__ Moments chunk_moments(const float (&x)[kChunk], int count) {
+    if (count <= 0) return Moments{0.0, 0.0, 0.0};
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) s += j < count ? static_cast<double>(x[j]) : 0.0;
+    const double mean = s / count;
+    double m2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+        const double d = static_cast<double>(x[j]) - mean;
+        m2 += j < count ? d * d : 0.0;
+    }
+    return Moments{static_cast<double>(count), mean, m2};
+}
+
+// grid = n * parts workgroups; workgroup (frame, part) covers passes part,
+// part + parts, ... of kSpan pixels and writes one partial per component.
+__global__ __launch_bounds__(kStatThreads) void motion_moments_kernel(const float *mv, int64_t hw,
+                                                                     int parts, Moments *partial) {
+    __shared__ Moments lds[2][kStatThreads / 64];
+    const int frame = blockIdx.x / parts;
+    const int part = blockIdx.x % parts;
+    const float *pu = mv + 2 * static_cast<int64_t>(frame) * hw;
+    const float *pv = pu + hw;
+    Moments mu{0.0, 0.0, 0.0}, mvv{0.0, 0.0, 0.0};
+    for (int64_t base = static_cast<int64_t>(part) * kSpan; base < hw;
+         base += static_cast<int64_t>(parts) * kSpan) {
+        float xu[kChunk], xv[kChunk];
+        int count = 0;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            const int64_t i = base + j * kStatThreads + threadIdx.x;  // coalesced
+            const bool in = i < hw;
+            xu[j] = in ? pu[i] : 0.0f;
+            xv[j] = in ? pv[i] : 0.0f;
+            count += in ? 1 : 0;
+        }
+        // in-range values are a prefix of the chunk (j increases with i)
+        mu = fold(mu, chunk_moments(xu, count));
+        mvv = fold(mvv, chunk_moments(xv, count));
+    }
+    mu = wave_fold(mu);
+    mvv = wave_fold(mvv);
+    const int wave = threadIdx.x / 64;
+    if (__lane_id() == 0) {
+        lds[0][wave] = mu;
+        lds[1][wave] = mvv;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        Moments m = lds[threadIdx.x][0];
+        for (int k = 1; k < kStatThreads / 64; ++k) m = fold(m, lds[threadIdx.x][k]);
+        partial[(static_cast<int64_t>(frame) * 2 + threadIdx.x) * parts + part] = m;
+    }
+}
+
+// One wavefront per frame and component folds the workgroup partials.
+__global__ __launch_bounds__(64) void motion_stats_final_kernel(const Moments *partial, int parts,
+                                                                double *stats) {
+    const int frame = blockIdx.x / 2, comp = blockIdx.x % 2;
+    const Moments *p = partial + (static_cast<int64_t>(frame) * 2 + comp) * parts;
+    Moments m{0.0, 0.0, 0.0};
+    for (int i = __lane_id(); i < parts; i += 64) m = fold(m, p[i]);
+    m = wave_fold(m);
+    if (__lane_id() == 0) {
+        stats[frame * 4 + 2 * comp] = m.mean;
+        stats[frame * 4 + 2 * comp + 1] = m.m2 / m.n;
+    }
+}
+
+int parts_for(int64_t hw) {
+    const int64_t passes = (hw + kSpan - 1) / kSpan;
+    return static_cast<int>(passes < kMaxParts ? passes : kMaxParts);
+}
+
+}  // namespace
+
+size_t motion_stats_workspace_bytes(int n, int h, int w) {
+    return sizeof(Moments) * 2 * static_cast<size_t>(n) *
+           parts_for(static_cast<int64_t>(h) * w);
+}
+
+hipError_t launch_motion_stats(const float *mv, int n, int h, int w, double *stats,
+                               void *workspace, hipStream_t stream) {
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const int parts = parts_for(hw);
+    Moments *partial = static_cast<Moments *>(workspace);
+    hipLaunchKernelGGL(motion_moments_kernel, dim3(static_cast<unsigned>(n) * parts),
+                       dim3(kStatThreads), 0, stream, mv, hw, parts, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(motion_stats_final_kernel, dim3(static_cast<unsigned>(n) * 2), dim3(64), 0,
+                       stream, partial, parts, stats);
+    return hipGetLastError();
+}
+
+}  // namespace exw

@@ -303,18 +303,24 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     const int ca = tx0 - (kSegW - 1) - reach;
     const int sc_lo = ca > 0 ? (ca + kSegW - 1) / kSegW : 0;
     const int sc_hi = min(a.segs - 1, (tx0 + kTileW - 1 + reach) / kSegW);
+    // Candidate i is row r_lo + (i >> sh), column sc_lo + (i & cm): the columns
+    // are padded to a power of two (at most 8 of them) so that no division is
+    // needed; padding columns are never hits.
     const int nsc = sc_hi - sc_lo + 1;
-    const int total = (r_hi - r_lo + 1) * nsc;
+    const int sh = nsc <= 1 ? 0 : 32 - __builtin_clz(static_cast<unsigned>(nsc - 1));
+    const int cm = (1 << sh) - 1;
+    const int total = (r_hi - r_lo + 1) << sh;
     const Box *fboxes = a.boxes + static_cast<int64_t>(in) * h * a.segs;
 
     auto box_of = [&](int i) -> Box {  // clamped: the load is always in bounds
         const int ic = min(i, total - 1);
-        return fboxes[static_cast<int64_t>(r_lo + ic / nsc) * a.segs + sc_lo + ic % nsc];
+        const int c = min(ic & cm, nsc - 1);
+        return fboxes[static_cast<int64_t>(r_lo + (ic >> sh)) * a.segs + sc_lo + c];
     };
     // Bit 0: the segment is near (its taps are scattered here); bit 1: home.
     auto classify = [&](const Box &bx, int i) -> int {
-        if (i >= total) return 0;
-        const int r = r_lo + i / nsc, sc = sc_lo + i % nsc;
+        if (i >= total || (i & cm) >= nsc) return 0;
+        const int r = r_lo + (i >> sh), sc = sc_lo + (i & cm);
         const bool home = a.gmv && (unsigned)(r - ty0) < (unsigned)TH && sc * kSegW / kTileW == tx;
         const bool near = bx.x_lo <= bx.x_hi && box_reach(bx, sc * kSegW, r) <= kFar &&
                           bx.x_hi >= tx0 && bx.x_lo < tx0 + kTileW && bx.y_hi >= ty0 &&
@@ -351,8 +357,8 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     for (int ch = 0; ch < CT; ++ch) iplane[ch] = img ? img + ch * hw : nullptr;
     auto load_seg = [&](int code, SegLoad<T, CT, KT> &d) {
         const int i = code >> 1;
-        const int y = r_lo + i / nsc;
-        const int x = (sc_lo + i % nsc) * kSegW + lane;
+        const int y = r_lo + (i >> sh);
+        const int x = (sc_lo + (i & cm)) * kSegW + lane;
         // lanes past the row end read its last pixel (always in bounds)
         const uint32_t pc = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + min(x, w - 1);
         d.u = *at(mu, pc);
@@ -372,8 +378,8 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
 
         const int i = code >> 1;  // wave-uniform
         const bool near = code & 1;
-        const int y = r_lo + i / nsc;
-        const int sx0 = (sc_lo + i % nsc) * kSegW;
+        const int y = r_lo + (i >> sh);
+        const int sx0 = (sc_lo + (i & cm)) * kSegW;
         const int x = sx0 + lane;
         const bool inx = x < w;
         PTaps t[KT];

@@ -55,6 +55,11 @@ __device__ __forceinline__ PixelPos decode_pixel(int tiles_x, int tiles_y, int w
     return q;
 }
 
+// v from lane + 1 (0 into lane 63): a DPP wavefront shift.
+__device__ __forceinline__ float shift_down1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
 __device__ __forceinline__ void count_invalid(uint32_t *count, int64_t plane, bool inside,
                                               bool valid) {
     // One atomic per wavefront that saw invalid pixels (frame borders only).
@@ -112,21 +117,62 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
             // pair starts one to the left and the tap takes its second element.
             const int xl = min(ax.i0, w - 2);
             const bool last = ax.i0 == w - 1;
-            const uint32_t o0 = static_cast<uint32_t>(ay.i0) * static_cast<uint32_t>(w) + xl;
-            const uint32_t o1 = static_cast<uint32_t>(ay.i1) * static_cast<uint32_t>(w) + xl;
             float vals[CT];
+            // Uniform wavefront: every lane of the row is valid with the integer
+            // tap offset of lane 0, so lane j's right-hand taps are lane j+1's
+            // left-hand taps. One aligned element load per row and channel plus
+            // a lane shift replaces the unaligned pair load; lane 63 fetches its
+            // right-hand taps itself.
+            const int offx = q.x - ax.i0, offy = q.y - ay.i0;
+            const int rx = __builtin_amdgcn_readfirstlane(offx);
+            const int ry = __builtin_amdgcn_readfirstlane(offy);
+            const bool uniform =
+                __ballot(!q.inside || (valid && offx == rx && offy == ry)) == ~0ull;
+            if (uniform) {
+                const int tx0 = q.x - static_cast<int>(threadIdx.x);
+                const uint32_t r0 = static_cast<uint32_t>(q.y - ry) * static_cast<uint32_t>(w);
+                const uint32_t r1 = static_cast<uint32_t>(ay.i1) * static_cast<uint32_t>(w);
+                // lanes past the row end read its last pixel (in bounds, unused)
+                const uint32_t xa = static_cast<uint32_t>(min(q.x - rx, w - 1));
+                const uint32_t xe = static_cast<uint32_t>(min(tx0 + kTileW - rx, w - 1));
+                float e0[CT], e1[CT];
 #pragma unroll
-            for (int ch = 0; ch < CT; ++ch) {
-                float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
-                if (valid) {
-                    load_pair(at(iplane[ch], o0), a0, b0);
-                    load_pair(at(iplane[ch], o1), a1, b1);
+                for (int ch = 0; ch < CT; ++ch) e0[ch] = e1[ch] = 0.0f;
+                if (threadIdx.x == kTileW - 1) {
+#pragma unroll
+                    for (int ch = 0; ch < CT; ++ch) {
+                        e0[ch] = to_f32(*at(iplane[ch], r0 + xe));
+                        e1[ch] = to_f32(*at(iplane[ch], r1 + xe));
+                    }
                 }
-                float acc = w00 * (last ? b0 : a0);
-                acc = fmaf(w01, b0, acc);
-                acc = fmaf(w10, last ? b1 : a1, acc);
-                acc = fmaf(w11, b1, acc);
-                vals[ch] = valid ? acc : 0.0f;
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) {
+                    const float a0 = to_f32(*at(iplane[ch], r0 + xa));
+                    const float a1 = to_f32(*at(iplane[ch], r1 + xa));
+                    float b0 = shift_down1(a0), b1 = shift_down1(a1);
+                    if (threadIdx.x == kTileW - 1) { b0 = e0[ch]; b1 = e1[ch]; }
+                    float acc = w00 * a0;
+                    acc = fmaf(w01, b0, acc);
+                    acc = fmaf(w10, a1, acc);
+                    acc = fmaf(w11, b1, acc);
+                    vals[ch] = acc;
+                }
+            } else {
+                const uint32_t o0 = static_cast<uint32_t>(ay.i0) * static_cast<uint32_t>(w) + xl;
+                const uint32_t o1 = static_cast<uint32_t>(ay.i1) * static_cast<uint32_t>(w) + xl;
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) {
+                    float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
+                    if (valid) {
+                        load_pair(at(iplane[ch], o0), a0, b0);
+                        load_pair(at(iplane[ch], o1), a1, b1);
+                    }
+                    float acc = w00 * (last ? b0 : a0);
+                    acc = fmaf(w01, b0, acc);
+                    acc = fmaf(w10, last ? b1 : a1, acc);
+                    acc = fmaf(w11, b1, acc);
+                    vals[ch] = valid ? acc : 0.0f;
+                }
             }
             T *const *op = oplane[0];
             uint8_t *mp = mplane[0];

@@ -134,7 +134,8 @@ class _Surface:
 
 def pan_rect_sequence(rng: np.random.Generator, n: int, h: int, w: int, *, kind: str = "rgba",
                       n_rects: int = 16, vmax: float = 32.0, pan_max: float = 3.0,
-                      rect_size: Sequence[int] = (32, 256), pan: Optional[Sequence[float]] = None):
+                      rect_size: Sequence[int] = (32, 256), pan: Optional[Sequence[float]] = None,
+                      truth_phases: Optional[Sequence[float]] = None):
     """Camera pan plus moving rectangles; returns ``(frames, mv, info)``.
 
     * Pan ``(px, py) ~ U(-pan_max, pan_max)^2`` px per frame (or ``pan``):
@@ -147,7 +148,9 @@ def pan_rect_sequence(rng: np.random.Generator, n: int, h: int, w: int, *, kind:
     * ``mv[i, :, y, x]`` is the velocity of the topmost surface at ``(x, y)``.
 
     ``kind`` is ``"rgb"`` (3 channels), ``"rgba"`` (4) or ``"gbuffer"`` (12,
-    in the order of ``GBUFFER_CHANNELS``).
+    in the order of ``GBUFFER_CHANNELS``). With ``truth_phases``, ``info["truth"]``
+    [N, K, C, H, W] holds the scene rendered at times ``i + s`` (the ground
+    truth of the frames predicted between rendered frames).
     """
     if pan is None:
         pan = rng.uniform(-pan_max, pan_max, size=2)
@@ -163,27 +166,40 @@ def pan_rect_sequence(rng: np.random.Generator, n: int, h: int, w: int, *, kind:
         rects.append((rw, rh, x0, y0, vel, _Surface(rng, kind, background=False)))
 
     c = bg.channels
-    frames = np.empty((n, c, h, w), dtype=np.float32)
-    mv = np.empty((n, 2, h, w), dtype=np.float32)
     xs = np.arange(w, dtype=np.float64)
     ys = np.arange(h, dtype=np.float64)
-    for i in range(n):
-        frame = bg.eval(xs - i * pan[0], ys - i * pan[1])
-        mv[i, 0] = np.float32(pan[0])
-        mv[i, 1] = np.float32(pan[1])
+
+    def render(t: float):
+        # the scene at time t (in rendered-frame intervals): image and motion
+        frame = bg.eval(xs - t * pan[0], ys - t * pan[1])
+        motion = np.empty((2, h, w), dtype=np.float32)
+        motion[0] = np.float32(pan[0])
+        motion[1] = np.float32(pan[1])
         for rw, rh, rx, ry, vel, surf in rects:
-            left = rx + i * vel[0]
-            top = ry + i * vel[1]
+            left = rx + t * vel[0]
+            top = ry + t * vel[1]
             xa, xb = max(0, math.ceil(left)), min(w, math.ceil(left + rw))
             ya, yb = max(0, math.ceil(top)), min(h, math.ceil(top + rh))
             if xa >= xb or ya >= yb:
                 continue
             frame[:, ya:yb, xa:xb] = surf.eval(xs[xa:xb] - left, ys[ya:yb] - top)
-            mv[i, 0, ya:yb, xa:xb] = np.float32(vel[0])
-            mv[i, 1, ya:yb, xa:xb] = np.float32(vel[1])
-        frames[i] = frame
+            motion[0, ya:yb, xa:xb] = np.float32(vel[0])
+            motion[1, ya:yb, xa:xb] = np.float32(vel[1])
+        return frame, motion
+
+    frames = np.empty((n, c, h, w), dtype=np.float32)
+    mv = np.empty((n, 2, h, w), dtype=np.float32)
+    for i in range(n):
+        frames[i], mv[i] = render(float(i))
     info = {"pan": pan.tolist(), "n_rects": n_rects, "vmax": vmax,
             "velocities": [r[4].tolist() for r in rects]}
+    if truth_phases is not None:
+        # the exact scene between rendered frames: what a perfect predictor shows
+        truth = np.empty((n, len(truth_phases), c, h, w), dtype=np.float32)
+        for i in range(n):
+            for k, s in enumerate(truth_phases):
+                truth[i, k] = render(i + float(s))[0]
+        info["truth"] = truth
     return frames, mv, info
 
 
@@ -228,12 +244,15 @@ CONFIGS = {
 
 
 def make_config(index: int, *, n: Optional[int] = None, h: Optional[int] = None,
-                w: Optional[int] = None, seed: Optional[int] = None) -> dict:
+                w: Optional[int] = None, seed: Optional[int] = None,
+                with_truth: bool = False) -> dict:
     """Draw the inputs of workload ``index`` (1..5), optionally at a reduced size.
 
     Returns a dict with ``src`` [N,C,H,W] float32, ``mv`` [N,2,H,W] float32,
     ``phases`` [K] float32, ``delta`` [N,2,H,W] float32 or None (the motion
-    perturbation of the L2 target), plus the spec. The default seed is
+    perturbation of the L2 target), ``truth`` [N,K,C,H,W] float32 (the scene
+    at times n + phase, pan-and-rectangle workloads with ``with_truth``) or
+    None, plus the spec. The default seed is
     ``1000 + index``. At a reduced size rectangle sizes shrink with the frame,
     velocities do not.
     """
@@ -250,12 +269,14 @@ def make_config(index: int, *, n: Optional[int] = None, h: Optional[int] = None,
         lo = max(4, int(round(32 * scale)))
         hi = max(lo, int(round(256 * scale)))
         src, mv, info = pan_rect_sequence(rng, n, h, w, kind=spec.kind, n_rects=spec.n_rects,
-                                          vmax=spec.vmax, rect_size=(lo, hi))
+                                          vmax=spec.vmax, rect_size=(lo, hi),
+                                          truth_phases=spec.phases if with_truth else None)
     delta = None
     if spec.delta_std > 0:
         delta = rng.normal(0.0, spec.delta_std, size=mv.shape).astype(np.float32)
+    truth = info.pop("truth", None)
     return {"spec": spec, "src": src, "mv": mv, "phases": np.asarray(spec.phases, np.float32),
-            "delta": delta, "info": info}
+            "delta": delta, "info": info, "truth": truth}
 
 
 def quantize(x: np.ndarray, dtype: str) -> np.ndarray:

@@ -147,6 +147,84 @@ def test_workspace_size():
     assert L.exw_warp_backward_workspace_bytes(9, 1, 3, 4, 5) == 0
 
 
+def stats(mv=FAKE, n=2, h=8, w=8, out=FAKE + (1 << 30), ws=FAKE + (2 << 30), ws_bytes=1 << 20):
+    L = _capi.lib()
+    return L.exw_motion_stats(mv, n, h, w, out, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(n=-1), INVALID, "negative size"),
+    (dict(h=0), INVALID, "empty frames"),
+    (dict(h=1 << 24), UNSUPPORTED, "2^24"),
+    (dict(h=1 << 16, w=1 << 15), UNSUPPORTED, "2^30"),
+    (dict(n=1 << 23), UNSUPPORTED, "2^23"),
+    (dict(mv=None), INVALID, "mv is NULL"),
+    (dict(mv=FAKE + 2), INVALID, "aligned"),
+    (dict(out=None), INVALID, "stats is NULL"),
+    (dict(out=FAKE + (1 << 30) + 4), INVALID, "aligned"),
+    (dict(ws=None), INVALID, "workspace is NULL"),
+    (dict(ws=FAKE + (2 << 30) + 64), INVALID, "256-byte aligned"),
+    (dict(ws_bytes=8), INVALID, "workspace has 8 bytes"),
+    (dict(out=FAKE + 64), INVALID, "stats overlaps input mv"),
+    (dict(ws=FAKE + (1 << 30)), INVALID, "stats overlaps output workspace"),
+])
+def test_motion_stats_rejects(kwargs, status, needle):
+    st = stats(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+def test_motion_stats_empty_batch_and_workspace_size():
+    assert stats(n=0, mv=None, out=None, ws=None, ws_bytes=0) == 0
+    L = _capi.lib()
+    # 48 bytes per workgroup partial (count, mean, M2 of both components in
+    # float64); ceil(H*W / 2048) partials per frame, at most 128
+    for (n, h, w) in [(1, 1, 1), (2, 45, 46), (3, 64, 64), (8, 1080, 1920), (4, 1440, 2560)]:
+        parts = min(-(-h * w // 2048), 128)
+        assert L.exw_motion_stats_workspace_bytes(n, h, w) == 48 * n * parts
+    assert L.exw_motion_stats_workspace_bytes(0, 4, 4) == 0
+
+
+def qual(pred=FAKE, truth=FAKE + (1 << 30), dtype=0, b=2, c=3, h=16, w=20, peak=1.0,
+         out=FAKE + (2 << 30), ws=FAKE + (3 << 30), ws_bytes=1 << 20):
+    return _capi.lib().exw_frame_quality(pred, truth, dtype, b, c, h, w, peak, out, ws, ws_bytes,
+                                         None)
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(dtype=7), INVALID, "unknown dtype"),
+    (dict(b=-1), INVALID, "negative size"),
+    (dict(peak=0.0), INVALID, "peak"),
+    (dict(peak=float("nan")), INVALID, "peak"),
+    (dict(c=0), INVALID, "channel count"),
+    (dict(h=10), INVALID, "11x11"),
+    (dict(w=3), INVALID, "11x11"),
+    (dict(h=1 << 24), UNSUPPORTED, "2^24"),
+    (dict(pred=None), INVALID, "pred is NULL"),
+    (dict(truth=FAKE + 2 + (1 << 30)), INVALID, "aligned"),
+    (dict(dtype=1, pred=FAKE + 1), INVALID, "aligned"),
+    (dict(out=FAKE + (2 << 30) + 4), INVALID, "aligned"),
+    (dict(ws=None), INVALID, "workspace is NULL"),
+    (dict(ws_bytes=8), INVALID, "workspace has 8 bytes"),
+    (dict(out=FAKE + 64), INVALID, "quality overlaps input pred"),
+    (dict(ws=FAKE + 256), INVALID, "workspace overlaps input pred"),
+])
+def test_frame_quality_rejects(kwargs, status, needle):
+    st = qual(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+def test_frame_quality_empty_batch_and_workspace_size():
+    assert qual(b=0, pred=None, truth=None, out=None, ws=None, ws_bytes=0) == 0
+    L = _capi.lib()
+    # 16 bytes (SSIM sum, squared-error sum) per strip of 64 x 66 SSIM positions
+    for (b, c, h, w) in [(1, 1, 11, 11), (2, 3, 76, 74), (3, 4, 77, 75), (24, 4, 1080, 1920)]:
+        strips = -(-(w - 10) // 64) * -(-(h - 10) // 66)
+        assert L.exw_frame_quality_workspace_bytes(b, c, h, w) == 16 * b * c * strips
+    assert L.exw_frame_quality_workspace_bytes(1, 1, 10, 40) == 0
+
+
 def test_missing_library_fails_loudly(tmp_path):
     code = ("import paper_2307_12607_amd._capi as c; c.LIB_PATH = '/nonexistent/libexwarp.so'; "
             "c._lib = None\ntry:\n    c.lib()\nexcept ImportError as e:\n    print('RAISED', e)")
