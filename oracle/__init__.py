@@ -11,6 +11,8 @@ path never does, and shares no code with it.
   scene-state quantities that accompany a warp.
 * ``quality``: per-frame MSE, PSNR and SSIM of a predicted frame against
   the ground truth.
+* ``decision_paths``: the decision tree of the frames shown between rendered
+  frames (Table V), chained warps W(P_i), and a fixed threshold policy.
 * ``warp_ref.c`` (+ ``ref_c``): the same definition as scalar C loops in
   float64, built with gcc (no HIP); used for the cross-check and as the timed
   CPU baseline.
