@@ -165,8 +165,8 @@ exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_
  * ------------------------------------------------------------------------ */
 
 /* Bytes of device workspace exw_motion_stats needs for N frames of H x W:
- * 48 bytes per workgroup partial, at most 128 partials per frame. Returns 0
- * for an empty batch. */
+ * 48 bytes per workgroup partial, one partial per 2048 pixels of a frame and
+ * at most 1024 per frame. Returns 0 for an empty batch. */
 size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w);
 
 /*
@@ -184,7 +184,7 @@ size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w);
  * reproducible bit for bit and does not cancel when the mean is large
  * against the spread. A non-finite value makes its component's mean and
  * variance non-finite. N = 0 does nothing; N > 0 with H = 0 or W = 0 is
- * EXW_ERROR_INVALID_VALUE (an empty frame has no variance); N >= 2^23 or
+ * EXW_ERROR_INVALID_VALUE (an empty frame has no variance); N >= 2^21 or
  * H*W > 2^30 is EXW_ERROR_UNSUPPORTED.
  */
 exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
@@ -227,6 +227,79 @@ size_t exw_frame_quality_workspace_bytes(int32_t b, int32_t c, int32_t h, int32_
 exw_status exw_frame_quality(const void *pred, const void *truth, exw_dtype dtype, int32_t b,
                              int32_t c, int32_t h, int32_t w, double peak, double *quality,
                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Decision paths (paper §IV-B, Table V).
+ *
+ * Between rendered frames F_t and F_t+1 the frames P_1, P_2, P_3 are shown
+ * at t + 1/4, 2/4, 3/4. Decision d1 (at t) shows W(F_t) at t + 1/4, or F_t
+ * again, after which the extrapolation E(F_t) is shown at t + 1/2. After
+ * d1 = warp, d2 (at t + 1/4) shows W(P_1) or E(F_t) at t + 1/2. At t + 1/2
+ * one more decision picks P_3: d3 (after d1 = extrapolate) between W(P_2) and
+ * P_2 again; d4 (after d2 = warp) and d5 (after d2 = extrapolate) between
+ * W(P_2) and E(P_1). The six paths are Table V's scenarios S1..S6.
+ * A warp of a predicted frame, W(P_i), is the forward warp of P_i with the
+ * motion of F_t at phase 1/4 (one display interval).
+ * ------------------------------------------------------------------------ */
+
+#define EXW_DECIDE_NONE (-1)
+#define EXW_DECIDE_WARP 0
+#define EXW_DECIDE_EXTRAPOLATE 1
+
+#define EXW_SHOW_REPEAT 0       /* the previous frame again (no new frame) */
+#define EXW_SHOW_WARP 1         /* W(source) */
+#define EXW_SHOW_EXTRAPOLATE 2  /* E(source), made by an extrapolator */
+
+#define EXW_FROM_RENDERED 0     /* F_t */
+#define EXW_FROM_P1 1
+#define EXW_FROM_P2 2
+
+typedef struct {
+    int32_t scenario;    /* 1..6: Table V's S1..S6 */
+    int32_t kind[3];     /* P_1..P_3: EXW_SHOW_* */
+    int32_t source[3];   /* P_1..P_3: EXW_FROM_* */
+    int32_t node[3];     /* decision node taken at t, t + 1/4, t + 1/2 (1..5; 0 = none) */
+    int32_t new_frames;  /* frames made between F_t and F_t+1; upsampling = new_frames + 1 */
+} exw_display_plan;
+
+/*
+ * The frames shown for the decisions d1 (at t), d2 (at t + 1/4; ignored,
+ * pass EXW_DECIDE_NONE, when d1 extrapolates) and d_last (at t + 1/2: node
+ * d3, d4 or d5), each EXW_DECIDE_WARP or EXW_DECIDE_EXTRAPOLATE (at d3,
+ * "extrapolate" means P_2 is shown again). Host-only; writes *plan.
+ * Returns EXW_ERROR_INVALID_VALUE for a NULL plan or an invalid decision.
+ */
+exw_status exw_decision_plan(int32_t d1, int32_t d2, int32_t d_last, exw_display_plan *plan);
+
+/*
+ * A fixed policy for the three decisions of one frame (a stand-in for the
+ * paper's learned predictor, §V, which needs trained weights): warp at a
+ * node when Var_x + Var_y of the frame's motion (motion_stats[1] +
+ * motion_stats[3], the layout of exw_motion_stats) is at most max_variance
+ * and the out-of-frame fraction of the warp that node would show is at most
+ * max_invalid; else extrapolate. invalid_fraction[0..2] are those fractions
+ * of W(F_t) at phases 1/4, 2/4, 3/4 (invalid_count / (H*W) of the forward
+ * warp); node d1 looks at [0], d2 at [1], the node at t + 1/2 at [2].
+ * Writes decisions[0..2] = (d1, d2 or EXW_DECIDE_NONE, d_last). Host-only;
+ * all pointers are host memory.
+ */
+exw_status exw_threshold_policy(const double *motion_stats, const double *invalid_fraction,
+                                double max_variance, double max_invalid, int32_t *decisions);
+
+/*
+ * Chained warps: out[0] = W(src, phase), out[i] = W(out[i-1], phase), each
+ * with the same motion mv (the warps W(P_i) of the decision paths, phase
+ * 1/4). Each step is the forward warp of exw_warp_forward_batched applied
+ * to the previous step's stored output (rounded to dtype).
+ *   src [N, C, H, W] dtype; mv [N, 2, H, W] float32;
+ *   out [S, N, C, H, W] dtype (step-major, so each step is a contiguous batch);
+ *   mask [S, N, H, W] uint8 or NULL; invalid_count [S, N] uint32 or NULL:
+ *   each step's own out-of-frame test.
+ *   steps S >= 1; phase finite. Same conventions and limits as the forward.
+ */
+exw_status exw_warp_chain(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                          int32_t w, const float *mv, float phase, int32_t steps, void *out,
+                          uint8_t *mask, uint32_t *invalid_count, void *stream);
 
 #ifdef __cplusplus
 }

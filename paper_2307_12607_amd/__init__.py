@@ -14,6 +14,9 @@ package marshals torch tensors to that ABI:
   scene-state feature the warp/extrapolate decision is taken on (§V).
 * ``frame_quality``: per-frame MSE, PSNR and SSIM against the ground truth,
   the quality terms of the decision's reward (§V).
+* ``warp_chain``, ``plan``, ``threshold_policy``, ``decision_path_frames``:
+  the decision paths of §IV-B / Table V (chained warps W(P_i) on the GPU,
+  the decision tree and a fixed policy in native host code).
 """
 
 from __future__ import annotations
@@ -27,8 +30,11 @@ from .binding import (  # noqa: F401
     exw_warp_backward,
     exw_warp_backward_batched,
     exw_warp_backward_workspace_bytes,
+    exw_decision_plan,
     exw_frame_quality,
     exw_frame_quality_workspace_bytes,
+    exw_threshold_policy,
+    exw_warp_chain,
     exw_motion_stats,
     exw_motion_stats_workspace_bytes,
     exw_warp_forward,
@@ -137,8 +143,71 @@ def frame_quality(pred: torch.Tensor, truth: torch.Tensor, peak: float = 1.0) ->
     return q.reshape(*lead, 3)
 
 
+def warp_chain(src: torch.Tensor, mv: torch.Tensor, phase: float = 0.25, steps: int = 3, *,
+               return_mask: bool = False, return_count: bool = False):
+    """Chained warps ``out[i] = W(out[i-1], phase)``, ``out[0] = W(src, phase)``:
+    ``out`` [S,N,C,H,W] (+ ``mask`` [S,N,H,W], ``invalid_count`` [S,N])."""
+    src = src.contiguous()
+    mv = mv.contiguous()
+    n, c, h, w = src.shape
+    out = torch.empty((steps, n, c, h, w), dtype=src.dtype, device=src.device)
+    mask = (torch.empty((steps, n, h, w), dtype=torch.uint8, device=src.device)
+            if return_mask else None)
+    cnt = torch.empty((steps, n), dtype=torch.int32, device=src.device) if return_count else None
+    exw_warp_chain(src, mv, phase, steps, out, mask, cnt)
+    res = [out] + ([mask] if return_mask else []) + ([cnt] if return_count else [])
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+_KINDS = {0: "repeat", 1: "warp", 2: "extrapolate"}
+_SOURCES = {0: "F", 1: "P1", 2: "P2"}
+WARP, EXTRAPOLATE, NONE = 0, 1, -1
+
+
+def plan(d1: int, d2, d_last: int) -> dict:
+    """The frames shown for decisions (d1, d2, d_last) (§IV-B, Table V):
+    ``{"scenario": "S1".."S6", "P1": (kind, source), "P2": ..., "P3": ...,
+    "nodes": (...), "new_frames": n}``."""
+    p = exw_decision_plan(d1, NONE if d2 is None else d2, d_last)
+    out = {"scenario": f"S{p.scenario}", "new_frames": p.new_frames,
+           "nodes": tuple(None if v == 0 else v for v in p.node)}
+    for i in range(3):
+        out[f"P{i + 1}"] = (_KINDS[p.kind[i]], _SOURCES[p.source[i]])
+    return out
+
+
+def threshold_policy(motion_stats, invalid_fraction, max_variance: float, max_invalid: float):
+    """Decisions ``(d1, d2 or None, d_last)`` of the fixed policy for one frame."""
+    d1, d2, d3 = exw_threshold_policy(motion_stats, invalid_fraction, max_variance, max_invalid)
+    return d1, (None if d2 == NONE else d2), d3
+
+
+def decision_path_frames(src: torch.Tensor, mv: torch.Tensor, path: dict, extrapolate=None):
+    """Make the frames P1, P2, P3 of a decision path (a ``plan`` result) on the
+    GPU: warps are the forward warp at phase 1/4 with the motion of ``src``;
+    ``extrapolate(frame) -> frame`` makes extrapolated frames (the paper's
+    extrapolation network is not part of this library; without it those
+    frames are None). Returns ``[P1, P2, P3]``, each [N,C,H,W] or None."""
+    made = {"F": src}
+    frames = []
+    for i in range(3):
+        kind, source = path[f"P{i + 1}"]
+        base = made[source]
+        if kind == "repeat":
+            f = base
+        elif kind == "warp":
+            f = None if base is None else warp(base, mv, (0.25,))[:, 0]
+        else:
+            f = None if (extrapolate is None or base is None) else extrapolate(base)
+        made[f"P{i + 1}"] = f
+        frames.append(f)
+    return frames
+
+
 __all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differentiable",
-           "motion_stats", "frame_quality", "exw_warp_forward", "exw_warp_forward_batched", "exw_warp_backward",
+           "motion_stats", "frame_quality", "warp_chain", "plan", "threshold_policy",
+           "decision_path_frames", "exw_warp_forward", "exw_warp_forward_batched", "exw_warp_backward",
            "exw_warp_backward_batched", "exw_warp_backward_workspace_bytes", "exw_motion_stats",
            "exw_motion_stats_workspace_bytes", "exw_frame_quality",
-           "exw_frame_quality_workspace_bytes"]
+           "exw_frame_quality_workspace_bytes", "exw_warp_chain", "exw_decision_plan",
+           "exw_threshold_policy"]

@@ -38,9 +38,25 @@ SIGNATURES = {
     "exw_motion_stats_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "exw_motion_stats": (ctypes.c_int, [_p, _i32, _i32, _i32, _p, _p, _sz, _p]),
     "exw_frame_quality_workspace_bytes": (_sz, [_i32, _i32, _i32, _i32]),
+    "exw_decision_plan": (ctypes.c_int, [_i32, _i32, _i32, _p]),
+    "exw_threshold_policy": (ctypes.c_int, [_p, _p, ctypes.c_double, ctypes.c_double, _p]),
+    "exw_warp_chain": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _i32, _p, _f, _i32, _p,
+                                      _p, _p, _p]),
     "exw_frame_quality": (ctypes.c_int, [_p, _p, ctypes.c_int, _i32, _i32, _i32, _i32,
                                          ctypes.c_double, _p, _p, _sz, _p]),
 }
+
+
+EXW_DECIDE_NONE, EXW_DECIDE_WARP, EXW_DECIDE_EXTRAPOLATE = -1, 0, 1
+EXW_SHOW_REPEAT, EXW_SHOW_WARP, EXW_SHOW_EXTRAPOLATE = 0, 1, 2
+EXW_FROM_RENDERED, EXW_FROM_P1, EXW_FROM_P2 = 0, 1, 2
+
+
+class DisplayPlan(ctypes.Structure):
+    """exw_display_plan of include/exwarp.h."""
+    _fields_ = [("scenario", ctypes.c_int32), ("kind", ctypes.c_int32 * 3),
+                ("source", ctypes.c_int32 * 3), ("node", ctypes.c_int32 * 3),
+                ("new_frames", ctypes.c_int32)]
 
 
 class ExwError(RuntimeError):

@@ -204,7 +204,49 @@ def exw_frame_quality(pred: torch.Tensor, truth: torch.Tensor, quality: torch.Te
     check(st, "exw_frame_quality")
 
 
+def exw_warp_chain(src: torch.Tensor, mv: torch.Tensor, phase: float, steps: int,
+                   out: torch.Tensor, mask: Optional[torch.Tensor] = None,
+                   invalid_count: Optional[torch.Tensor] = None, stream=None) -> None:
+    """src [N,C,H,W], mv [N,2,H,W] f32 -> out [S,N,C,H,W] (step-major), mask
+    [S,N,H,W] u8, invalid_count [S,N] u32/i32: out[i] = W(out[i-1], phase)."""
+    dev = src.device
+    _dev(src, "src", dev)
+    n, c, h, w = src.shape
+    dt = src.dtype
+    _expect(mv, "mv", (n, 2, h, w), torch.float32, dev)
+    _expect(out, "out", (steps, n, c, h, w), dt, dev)
+    _expect(mask, "mask", (steps, n, h, w), torch.uint8, dev)
+    if invalid_count is not None:
+        _dev(invalid_count, "invalid_count", dev)
+        if tuple(invalid_count.shape) != (steps, n) or invalid_count.dtype not in (torch.int32,
+                                                                                 torch.uint32):
+            raise ValueError("invalid_count must be [S, N] int32/uint32")
+    st = lib().exw_warp_chain(_ptr(src), exw_dtype(dt), n, c, h, w, _ptr(mv),
+                              ctypes.c_float(phase), steps, _ptr(out), _ptr(mask),
+                              _ptr(invalid_count), _stream(dev, stream))
+    check(st, "exw_warp_chain")
+
+
+def exw_decision_plan(d1: int, d2: int, d_last: int) -> "_capi.DisplayPlan":
+    """Host-only: the frames shown for decisions (d1, d2, d_last)."""
+    plan = _capi.DisplayPlan()
+    check(lib().exw_decision_plan(d1, d2, d_last, ctypes.byref(plan)), "exw_decision_plan")
+    return plan
+
+
+def exw_threshold_policy(motion_stats, invalid_fraction, max_variance: float,
+                         max_invalid: float) -> tuple:
+    """Host-only: (d1, d2, d_last) of the fixed policy for one frame."""
+    st = (ctypes.c_double * 4)(*[float(v) for v in motion_stats])
+    inv = (ctypes.c_double * 3)(*[float(v) for v in invalid_fraction])
+    dec = (ctypes.c_int32 * 3)()
+    check(lib().exw_threshold_policy(st, inv, ctypes.c_double(max_variance),
+                                     ctypes.c_double(max_invalid), dec), "exw_threshold_policy")
+    return tuple(dec)
+
+
 __all__ = ["ExwError", "exw_dtype", "exw_warp_forward_batched", "exw_warp_forward",
            "exw_warp_backward_workspace_bytes", "exw_warp_backward_batched", "exw_warp_backward",
            "exw_motion_stats_workspace_bytes", "exw_motion_stats",
-           "exw_frame_quality_workspace_bytes", "exw_frame_quality", "_capi"]
+           "exw_frame_quality_workspace_bytes", "exw_frame_quality", "exw_warp_chain",
+           "exw_decision_plan", "exw_threshold_policy", "_capi"]

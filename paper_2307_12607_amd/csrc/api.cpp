@@ -29,6 +29,19 @@ exw_status succeed() {
     return EXW_SUCCESS;
 }
 
+}  // namespace
+
+namespace exw {
+
+exw_status report(exw_status st, const char *msg) {
+    if (st == EXW_SUCCESS) return succeed();
+    return fail(st, "%s", msg);
+}
+
+}  // namespace exw
+
+namespace {
+
 size_t dtype_size(int dtype) {
     switch (dtype) {
     case EXW_F32: return 4;
@@ -287,8 +300,8 @@ exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, do
     const uint64_t hw = uint64_t(h) * uint64_t(w);
     if (hw > (uint64_t(1) << 30))
         return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu > 2^30", (unsigned long long)hw);
-    // the first pass runs at most 128 workgroups per frame in a 1-D grid
-    if (n >= (1 << 23)) return fail(EXW_ERROR_UNSUPPORTED, "frame count %d >= 2^23", n);
+    // the first pass runs at most 1024 workgroups per frame in a 1-D grid
+    if (n >= (1 << 21)) return fail(EXW_ERROR_UNSUPPORTED, "frame count %d >= 2^21", n);
     EXW_TRY(check_ptr("mv", mv, 4, true));
     EXW_TRY(check_ptr("stats", stats, 8, true));
     EXW_TRY(check_ptr("workspace", workspace, 256, true));
@@ -351,6 +364,46 @@ exw_status exw_frame_quality(const void *pred, const void *truth, exw_dtype dtyp
     return launched(exw::launch_quality(dtype, pred, truth, b, c, h, w, peak, quality, workspace,
                                         static_cast<hipStream_t>(stream)),
                     "frame quality launch");
+}
+
+exw_status exw_warp_chain(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                          int32_t w, const float *mv, float phase, int32_t steps, void *out,
+                          uint8_t *mask, uint32_t *invalid_count, void *stream) {
+    if (steps < 1) return fail(EXW_ERROR_INVALID_VALUE, "steps %d < 1", steps);
+    Checked ck;
+    EXW_TRY(check_common(dtype, n, c, h, w, &phase, 1, &ck));
+    const uint64_t step_out = ck.img_elems;  // one step: [N, C, H, W]
+    if (step_out * uint64_t(steps) > kMaxElems)
+        return fail(EXW_ERROR_UNSUPPORTED, "chain too large (%llu output elements)",
+                    (unsigned long long)(step_out * uint64_t(steps)));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t ns = uint64_t(n) * uint64_t(steps);
+    EXW_TRY(check_ptr("invalid_count", invalid_count, 4, false));
+    if (ck.empty) {
+        if (invalid_count && ns > 0)
+            return launched(exw::launch_zero_u32(invalid_count, int64_t(ns), st), "zero count");
+        return succeed();
+    }
+    EXW_TRY(check_ptr("src", src, ck.esize, true));
+    EXW_TRY(check_ptr("mv", mv, 4, true));
+    EXW_TRY(check_ptr("out", out, ck.esize, true));
+    EXW_TRY(check_ptr("mask", mask, 1, false));
+    const Span ins[] = {span("src", src, ck.img_elems * ck.esize),
+                        span("mv", mv, ck.mv_elems * 4)};
+    const Span outs[] = {span("out", out, step_out * uint64_t(steps) * ck.esize),
+                         span("mask", mask, ns * ck.hw),
+                         span("invalid_count", invalid_count, ns * 4)};
+    EXW_TRY(check_disjoint(outs, 3, ins, 2));
+    char *o = static_cast<char *>(out);
+    for (int i = 0; i < steps; ++i) {
+        const void *in = i == 0 ? src : o + (i - 1) * step_out * ck.esize;
+        hipError_t e = exw::launch_forward(
+            dtype, in, mv, ck.shape, o + i * step_out * ck.esize,
+            mask ? mask + uint64_t(i) * n * ck.hw : nullptr,
+            invalid_count ? invalid_count + uint64_t(i) * n : nullptr, st);
+        if (e != hipSuccess) return launched(e, "chained warp launch");
+    }
+    return succeed();
 }
 
 }  // extern "C"

@@ -6,7 +6,13 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "exwarp.h"
+
 namespace exw {
+
+// Record the calling thread's last error (or clear it on success) for host
+// entry points outside api.cpp; returns st.
+exw_status report(exw_status st, const char *msg);
 
 struct WarpShape {
     int n, c, h, w, k;

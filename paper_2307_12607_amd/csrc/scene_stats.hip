@@ -19,7 +19,7 @@ namespace {
 constexpr int kStatThreads = 256;
 constexpr int kChunk = 8;                          // values per thread, per component
 constexpr int kSpan = kStatThreads * kChunk;       // pixels per workgroup pass
-constexpr int kMaxParts = 128;                     // workgroups per frame, at most
+constexpr int kMaxParts = 1024;                    // workgroups per frame, at most
 
 struct Moments {
     double n, mean, m2;

@@ -157,7 +157,7 @@ def stats(mv=FAKE, n=2, h=8, w=8, out=FAKE + (1 << 30), ws=FAKE + (2 << 30), ws_
     (dict(h=0), INVALID, "empty frames"),
     (dict(h=1 << 24), UNSUPPORTED, "2^24"),
     (dict(h=1 << 16, w=1 << 15), UNSUPPORTED, "2^30"),
-    (dict(n=1 << 23), UNSUPPORTED, "2^23"),
+    (dict(n=1 << 21), UNSUPPORTED, "2^21"),
     (dict(mv=None), INVALID, "mv is NULL"),
     (dict(mv=FAKE + 2), INVALID, "aligned"),
     (dict(out=None), INVALID, "stats is NULL"),
@@ -178,9 +178,10 @@ def test_motion_stats_empty_batch_and_workspace_size():
     assert stats(n=0, mv=None, out=None, ws=None, ws_bytes=0) == 0
     L = _capi.lib()
     # 48 bytes per workgroup partial (count, mean, M2 of both components in
-    # float64); ceil(H*W / 2048) partials per frame, at most 128
-    for (n, h, w) in [(1, 1, 1), (2, 45, 46), (3, 64, 64), (8, 1080, 1920), (4, 1440, 2560)]:
-        parts = min(-(-h * w // 2048), 128)
+    # float64); ceil(H*W / 2048) partials per frame, at most 1024
+    for (n, h, w) in [(1, 1, 1), (2, 45, 46), (3, 64, 64), (8, 1080, 1920), (4, 1440, 2560),
+                      (2, 2160, 3840)]:
+        parts = min(-(-h * w // 2048), 1024)
         assert L.exw_motion_stats_workspace_bytes(n, h, w) == 48 * n * parts
     assert L.exw_motion_stats_workspace_bytes(0, 4, 4) == 0
 
@@ -223,6 +224,32 @@ def test_frame_quality_empty_batch_and_workspace_size():
         strips = -(-(w - 10) // 64) * -(-(h - 10) // 66)
         assert L.exw_frame_quality_workspace_bytes(b, c, h, w) == 16 * b * c * strips
     assert L.exw_frame_quality_workspace_bytes(1, 1, 10, 40) == 0
+
+
+def chain(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phase=0.25, steps=3,
+          out=FAKE + (2 << 30), mask=None, count=None):
+    return _capi.lib().exw_warp_chain(src, dtype, n, c, h, w, mv, F(phase), steps, out, mask,
+                                      count, None)
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(steps=0), INVALID, "steps 0 < 1"),
+    (dict(phase=float("inf")), INVALID, "not finite"),
+    (dict(c=65), UNSUPPORTED, "channel count"),
+    (dict(src=None), INVALID, "src is NULL"),
+    (dict(out=FAKE + 100), INVALID, "out overlaps input src"),
+    (dict(mask=FAKE + (2 << 30) + 3 * 3 * 64 * 4 - 8), INVALID, "out overlaps output mask"),
+    (dict(count=FAKE + (1 << 30) + 4), INVALID, "overlaps input mv"),
+    (dict(n=1 << 20, h=1 << 10, w=1 << 10, steps=4), UNSUPPORTED, "too large"),
+])
+def test_chain_rejects(kwargs, status, needle):
+    st = chain(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+def test_chain_empty_batch_is_a_no_op():
+    assert chain(n=0, src=None, mv=None, out=None) == 0
 
 
 def test_missing_library_fails_loudly(tmp_path):
