@@ -166,7 +166,7 @@ exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_
 
 /* Bytes of device workspace exw_motion_stats needs for N frames of H x W:
  * 48 bytes per workgroup partial, one partial per 2048 pixels of a frame and
- * at most 1024 per frame. Returns 0 for an empty batch. */
+ * at most 256 per frame. Returns 0 for an empty batch. */
 size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w);
 
 /*

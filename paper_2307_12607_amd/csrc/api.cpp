@@ -300,7 +300,7 @@ exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, do
     const uint64_t hw = uint64_t(h) * uint64_t(w);
     if (hw > (uint64_t(1) << 30))
         return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu > 2^30", (unsigned long long)hw);
-    // the first pass runs at most 1024 workgroups per frame in a 1-D grid
+    // the first pass runs at most 256 workgroups per frame in a 1-D grid
     if (n >= (1 << 21)) return fail(EXW_ERROR_UNSUPPORTED, "frame count %d >= 2^21", n);
     EXW_TRY(check_ptr("mv", mv, 4, true));
     EXW_TRY(check_ptr("stats", stats, 8, true));

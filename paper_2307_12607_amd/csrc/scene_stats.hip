@@ -19,7 +19,7 @@ namespace {
 constexpr int kStatThreads = 256;
 constexpr int kChunk = 8;                          // values per thread, per component
 constexpr int kSpan = kStatThreads * kChunk;       // pixels per workgroup pass
-constexpr int kMaxParts = 1024;                    // workgroups per frame, at most
+constexpr int kMaxParts = 256;                     // workgroups per frame, at most
 
 struct Moments {
     double n, mean, m2;
@@ -75,21 +75,33 @@ __global__ __launch_bounds__(kStatThreads) void motion_moments_kernel(const floa
     const float *pu = mv + 2 * static_cast<int64_t>(frame) * hw;
     const float *pv = pu + hw;
     Moments mu{0.0, 0.0, 0.0}, mvv{0.0, 0.0, 0.0};
-    for (int64_t base = static_cast<int64_t>(part) * kSpan; base < hw;
-         base += static_cast<int64_t>(parts) * kSpan) {
-        float xu[kChunk], xv[kChunk];
-        int count = 0;
+    const int64_t stride = static_cast<int64_t>(parts) * kSpan;
+    // The next chunk is loaded while the current one is folded.
+    float xu[kChunk], xv[kChunk];
+    auto load = [&](int64_t base, float (&u)[kChunk], float (&v)[kChunk]) {
 #pragma unroll
         for (int j = 0; j < kChunk; ++j) {
             const int64_t i = base + j * kStatThreads + threadIdx.x;  // coalesced
             const bool in = i < hw;
-            xu[j] = in ? pu[i] : 0.0f;
-            xv[j] = in ? pv[i] : 0.0f;
-            count += in ? 1 : 0;
+            u[j] = in ? pu[i] : 0.0f;
+            v[j] = in ? pv[i] : 0.0f;
         }
+    };
+    int64_t base = static_cast<int64_t>(part) * kSpan;
+    if (base < hw) load(base, xu, xv);
+    for (; base < hw; base += stride) {
+        float nu[kChunk], nv[kChunk];
+        if (base + stride < hw) load(base + stride, nu, nv);
         // in-range values are a prefix of the chunk (j increases with i)
+        const int64_t left = (hw - base - threadIdx.x + kStatThreads - 1) / kStatThreads;
+        const int count = static_cast<int>(left < kChunk ? left : kChunk);
         mu = fold(mu, chunk_moments(xu, count));
         mvv = fold(mvv, chunk_moments(xv, count));
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            xu[j] = nu[j];
+            xv[j] = nv[j];
+        }
     }
     mu = wave_fold(mu);
     mvv = wave_fold(mvv);

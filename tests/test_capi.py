@@ -178,10 +178,10 @@ def test_motion_stats_empty_batch_and_workspace_size():
     assert stats(n=0, mv=None, out=None, ws=None, ws_bytes=0) == 0
     L = _capi.lib()
     # 48 bytes per workgroup partial (count, mean, M2 of both components in
-    # float64); ceil(H*W / 2048) partials per frame, at most 1024
+    # float64); ceil(H*W / 2048) partials per frame, at most 256
     for (n, h, w) in [(1, 1, 1), (2, 45, 46), (3, 64, 64), (8, 1080, 1920), (4, 1440, 2560),
                       (2, 2160, 3840)]:
-        parts = min(-(-h * w // 2048), 1024)
+        parts = min(-(-h * w // 2048), 256)
         assert L.exw_motion_stats_workspace_bytes(n, h, w) == 48 * n * parts
     assert L.exw_motion_stats_workspace_bytes(0, 4, 4) == 0
 

@@ -68,7 +68,7 @@ def test_stats_full_size_workload_2():
 
 
 def test_stats_many_passes_per_workgroup():
-    # 2160 x 3840 = 8.3 M pixels: 4050 passes of 2048 over 1024 workgroups
+    # 2160 x 3840 = 8.3 M pixels: 4050 passes of 2048 over 256 workgroups
     dev = need_gpu()
     mv = np.random.default_rng(5).uniform(-40, 40, (2, 2, 2160, 3840)).astype(np.float32)
     announce("motion stats 4K", mv.shape)
