@@ -732,12 +732,18 @@ hipError_t run_generic(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
 
 // ---------------------------------------------------------------- launchers
 
-int tile_rows_for(int c) {
-    // One wavefront per 128 x 2 tile: 1 KB of float32 accumulators per
-    // channel (4 KB for RGBA, 12 KB for a 12-channel G-buffer); measured
-    // faster than 128 x 4, 128 x 1 and 64 x 2 (more wavefronts in flight).
-    (void)c;
-    return 2;
+template <typename T> constexpr int dtype_code() { return 2; }
+template <> constexpr int dtype_code<float>() { return 0; }
+template <> constexpr int dtype_code<_Float16>() { return 1; }
+
+int tile_rows_for(int c, int dtype) {
+    // One wavefront per 128 x TH tile of float32 accumulators (1 KB per
+    // channel and row pair). Taller tiles replay fewer segments (3.5 replays
+    // per segment at TH = 2, 2.9 at TH = 3, 2.5 at TH = 4 on workload 2) but
+    // hold more LDS per wavefront; measured on workload 2, TH = 3 is fastest
+    // for float32 frames with up to four channels and TH = 2 for 16-bit
+    // frames (TH = 4 and 128 x 1 were slower in both).
+    return (dtype == 0 && c <= 4) ? 3 : 2;
 }
 
 template <typename T, int CT, int KT>
@@ -807,7 +813,7 @@ hipError_t run_typed(const void *src, const float *mv, const WarpShape &s, const
     a.info = reinterpret_cast<FrameInfo *>(ws.info);
     a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
     a.segs = (s.w + kSegW - 1) / kSegW;
-    a.tile_h = tile_rows_for(s.c);
+    a.tile_h = tile_rows_for(s.c, dtype_code<T>());
     a.tiles_x = (s.w + kTileW - 1) / kTileW;
     a.tiles_y = (s.h + a.tile_h - 1) / a.tile_h;
     for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
