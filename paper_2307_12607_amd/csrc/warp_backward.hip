@@ -382,13 +382,8 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
             for (int ch = 0; ch < CT; ++ch) d.g[k][ch] = *at(gplane[k][ch], pc);
     };
 
-    SegLoad<T, CT, KT> cur, nxt;
-    int code = next_seg();
-    if (code >= 0) load_seg(code, cur);
-    while (code >= 0) {
-        const int ncode = next_seg();
-        if (ncode >= 0) load_seg(ncode, nxt);
-
+    // Replay of one segment (code from next_seg, loads from load_seg).
+    auto process = [&](const int code, const SegLoad<T, CT, KT> &cur) {
         const int i = code >> 1;  // wave-uniform
         const bool near = code & 1;
         const int y = r_lo + (i >> sh);
@@ -423,13 +418,12 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         if (near) {  // wave-uniform; far segments are scattered by pass 3
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                const int lx0 = t[k].ax.i0 - tx0, lx1 = t[k].ax.i1 - tx0;
-                const int ly0 = t[k].ay.i0 - ty0, ly1 = t[k].ay.i1 - ty0;
-                const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
-                const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
-                const bool iny0 = (unsigned)ly0 < (unsigned)TH;
-                const bool iny1 = (unsigned)ly1 < (unsigned)TH;
-                const bool any = t[k].valid && (inx0 || inx1) && (iny0 || iny1);
+                // A tap lies in the tile iff the first tap is at most one
+                // column (row) before it: the second is the first + 1, or the
+                // same at the last column (row).
+                const int lx0 = t[k].ax.i0 - tx0, ly0 = t[k].ay.i0 - ty0;
+                const bool any = t[k].valid && (unsigned)(lx0 + 1) < (unsigned)(kTileW + 1) &&
+                                 (unsigned)(ly0 + 1) < (unsigned)(TH + 1);
                 const unsigned long long any_m = __ballot(any);
                 if (any_m == 0ull) continue;  // wave-uniform
                 // Uniform offset: that of the first lane with an in-tile tap.
@@ -483,6 +477,11 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                 // Lanes off the uniform pattern (motion boundaries): LDS atomics.
                 if (__ballot(any && !uni)) {
                     if (any && !uni) {
+                        const int lx1 = t[k].ax.i1 - tx0, ly1 = t[k].ay.i1 - ty0;
+                        const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
+                        const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
+                        const bool iny0 = (unsigned)ly0 < (unsigned)TH;
+                        const bool iny1 = (unsigned)ly1 < (unsigned)TH;
 #pragma unroll
                         for (int ch = 0; ch < CT; ++ch) {
                             const float gg = g[k][ch];
@@ -499,6 +498,18 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                 }
             }
         }
+    };
+
+    // The next segment's loads are in flight while the current one is
+    // replayed. (Alternating two buffers without the copy needs more
+    // registers and was measured slower for 16-bit frames.)
+    SegLoad<T, CT, KT> cur, nxt;
+    int code = next_seg();
+    if (code >= 0) load_seg(code, cur);
+    while (code >= 0) {
+        const int ncode = next_seg();
+        if (ncode >= 0) load_seg(ncode, nxt);
+        process(code, cur);
         code = ncode;
         cur = nxt;
     }

@@ -34,11 +34,12 @@ __device__ __forceinline__ int xcd_tile_index(int b, int nblocks) {
 // displacement d:
 //   ok  <=> 0 <= p - d <= size-1, evaluated as p-(size-1) <= d <= p on float32
 //           values, which is exact (p and size-1 are integers below 2^24);
-//   i0  = floor(p - d) (exact), i1 = min(i0 + 1, size - 1);
-//   f   = (p - d) - i0, the weight of i1 (float32; exact except when d lies
-//         in (-1, 0) and d + 1 rounds).
+//   i0  = floor(p - d) = p - ceil(d) (exact), i1 = min(i0 + 1, size - 1);
+//   f   = (p - d) - i0 = ceil(d) - d, the weight of i1 (float32; exact except
+//         when d lies in (0, 1) and 1 - d rounds).
 // The absolute position p - d is never formed in float32: at p ~ 4000 that
-// would lose up to 2^-12 px.
+// would lose up to 2^-12 px. When ok is false the fields are those of d = 0
+// (i0 = p, f = 0): finite, but not a tap of the warp.
 struct Axis {
     int i0, i1;
     float f;
@@ -48,13 +49,12 @@ struct Axis {
 __device__ __forceinline__ Axis split_axis(float d, int p, int size) {
     Axis a;
     a.ok = (d <= static_cast<float>(p)) && (d >= static_cast<float>(p - (size - 1)));
-    const float dc = a.ok ? d : 0.0f;  // keeps the integer conversion in range
-    const float di = floorf(dc);
-    const float df = dc - di;          // > 0 exactly when d is not an integer
-    const int base = p - static_cast<int>(di);
-    const bool frac = df > 0.0f;
-    a.i0 = frac ? base - 1 : base;
-    a.f = frac ? 1.0f - df : 0.0f;
+    // Lanes that are not ok get the split of d = 0, so every field stays
+    // finite (weights of invalid lanes are multiplied by zero gradients).
+    const float dc = a.ok ? d : 0.0f;
+    const float c = ceilf(dc);
+    a.i0 = p - static_cast<int>(c);
+    a.f = c - dc;
     a.i1 = min(a.i0 + 1, size - 1);
     return a;
 }
