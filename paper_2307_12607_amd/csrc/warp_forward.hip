@@ -135,15 +135,23 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
                 // lanes past the row end read its last pixel (in bounds, unused)
                 const uint32_t xa = static_cast<uint32_t>(min(q.x - rx, w - 1));
                 const uint32_t xe = static_cast<uint32_t>(min(tx0 + kTileW - rx, w - 1));
+                // Lane 63's right-hand taps (2 rows x C channels) are fetched by
+                // lanes 0 .. 2C-1 in one load instruction and read back as
+                // wave-uniform values.
+                float ex = 0.0f;
+                if (threadIdx.x < 2 * CT) {
+                    const int lq = threadIdx.x;
+                    const T *pl = iplane[0];
+#pragma unroll
+                    for (int ch = 1; ch < CT; ++ch)
+                        if (lq % CT == ch) pl = iplane[ch];
+                    ex = to_f32(*at(pl, (lq < CT ? r0 : r1) + xe));
+                }
                 float e0[CT], e1[CT];
 #pragma unroll
-                for (int ch = 0; ch < CT; ++ch) e0[ch] = e1[ch] = 0.0f;
-                if (threadIdx.x == kTileW - 1) {
-#pragma unroll
-                    for (int ch = 0; ch < CT; ++ch) {
-                        e0[ch] = to_f32(*at(iplane[ch], r0 + xe));
-                        e1[ch] = to_f32(*at(iplane[ch], r1 + xe));
-                    }
+                for (int ch = 0; ch < CT; ++ch) {
+                    e0[ch] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), ch));
+                    e1[ch] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), CT + ch));
                 }
 #pragma unroll
                 for (int ch = 0; ch < CT; ++ch) {
