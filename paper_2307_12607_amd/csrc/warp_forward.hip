@@ -68,6 +68,90 @@ __device__ __forceinline__ void count_invalid(uint32_t *count, int64_t plane, bo
         atomicAdd(count + plane, static_cast<uint32_t>(__popcll(bal)));
 }
 
+// The uniform gather of all K phases at once, if every lane of the wavefront
+// is in the frame and every phase is uniform (see warp_forward_kernel);
+// returns false, having done nothing, otherwise (all lanes must take part in
+// the lane shifts: a shift from an inactive lane reads zero). Lanes 0 .. 2CK-1 fetch lane 63's right-hand taps of
+// every phase, row and channel in one load instruction. Only the fractions
+// stay in registers between the uniformity test and the blend; tap rows and
+// columns are recomputed from the wave-uniform offsets.
+template <typename T, int CT, int KT>
+__device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const PixelPos &q, float u,
+                                                   float v, const T *img, int64_t hw,
+                                                   uint32_t p) {
+    const int w = a.w, h = a.h;
+    float fx[KT], fy[KT];
+    int rx[KT], ry[KT];
+    bool uni = true;
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        const Axis ax = split_axis(a.s[j] * u, q.x, w);
+        const Axis ay = split_axis(a.s[j] * v, q.y, h);
+        const int offx = q.x - ax.i0, offy = q.y - ay.i0;
+        rx[j] = __builtin_amdgcn_readfirstlane(offx);
+        ry[j] = __builtin_amdgcn_readfirstlane(offy);
+        // every lane in the frame: the lane shifts below read all 64 lanes
+        uni = uni && q.inside && ax.ok && ay.ok && offx == rx[j] && offy == ry[j];
+        fx[j] = ax.f;
+        fy[j] = ay.f;
+    }
+    if (__ballot(uni) != ~0ull) return false;
+    const int tx0 = q.x - static_cast<int>(threadIdx.x);
+    // tap rows (wave-uniform) and columns of phase j
+    auto row0 = [&](int j) { return static_cast<uint32_t>(q.y - ry[j]) * static_cast<uint32_t>(w); };
+    auto row1 = [&](int j) {
+        return static_cast<uint32_t>(min(q.y - ry[j] + 1, h - 1)) * static_cast<uint32_t>(w);
+    };
+    float ex = 0.0f;
+    if (threadIdx.x < 2 * CT * KT) {
+        const int lq = threadIdx.x;
+        const int jq = lq / (2 * CT), rq = (lq / CT) % 2, cq = lq % CT;
+        int ryq = ry[0], rxq = rx[0];
+#pragma unroll
+        for (int j = 1; j < KT; ++j)
+            if (jq == j) { ryq = ry[j]; rxq = rx[j]; }
+        const int rowq = rq ? min(q.y - ryq + 1, h - 1) : q.y - ryq;
+        const uint32_t off = static_cast<uint32_t>(rowq) * static_cast<uint32_t>(w) +
+                             static_cast<uint32_t>(min(tx0 + kTileW - rxq, w - 1));
+        ex = to_f32(*at(img + cq * hw, off));
+    }
+    float a0[KT][CT], a1[KT][CT];
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        const uint32_t xa = static_cast<uint32_t>(q.x - rx[j]);  // in the row: every lane is valid
+        const uint32_t o0 = row0(j) + xa, o1 = row1(j) + xa;
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) {
+            a0[j][ch] = to_f32(*at(img + ch * hw, o0));
+            a1[j][ch] = to_f32(*at(img + ch * hw, o1));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        const float w00 = (1.0f - fx[j]) * (1.0f - fy[j]);
+        const float w01 = fx[j] * (1.0f - fy[j]);
+        const float w10 = (1.0f - fx[j]) * fy[j];
+        const float w11 = fx[j] * fy[j];
+        const int64_t plane = static_cast<int64_t>(q.in) * KT + j;
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) {
+            float b0 = shift_down1(a0[j][ch]), b1 = shift_down1(a1[j][ch]);
+            if (threadIdx.x == kTileW - 1) {
+                b0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), j * 2 * CT + ch));
+                b1 = __int_as_float(
+                    __builtin_amdgcn_readlane(__float_as_int(ex), j * 2 * CT + CT + ch));
+            }
+            float acc = w00 * a0[j][ch];
+            acc = fmaf(w01, b0, acc);
+            acc = fmaf(w10, a1[j][ch], acc);
+            acc = fmaf(w11, b1, acc);
+            *at(a.out + (plane * CT + ch) * hw, p) = from_f32<T>(acc);
+        }
+        if (a.mask) *at(a.mask + plane * hw, p) = 1;  // every inside lane is valid
+    }
+    return true;  // no invalid pixel: the zeroed counts stay as they are
+}
+
 // Channel count CT and phase count KT known at compile time; requires W >= 2
 // (paired horizontal loads). One phase at a time: its gathers, then its
 // stores. Addresses are 32-bit offsets inside a plane added to per-plane base
@@ -101,6 +185,12 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
         for (int ch = 0; ch < CT; ++ch) oplane[j][ch] = a.out + (plane * CT + ch) * hw;
         mplane[j] = a.mask ? a.mask + plane * hw : nullptr;
     }
+    // Every phase uniform and every lane in the frame (smooth motion: nearly
+    // every wavefront): the gathers of all K phases are issued together, one
+    // memory round trip instead of K.
+    if constexpr (2 * CT * KT <= kTileW) {
+        if (all_phases_uniform<T, CT, KT>(a, q, u, v, img, hw, p)) return;
+    }
 #pragma unroll 1
     for (int j = 0; j < KT; ++j) {
         // phase j without dynamic indexing of the argument arrays
@@ -126,8 +216,10 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
             const int offx = q.x - ax.i0, offy = q.y - ay.i0;
             const int rx = __builtin_amdgcn_readfirstlane(offx);
             const int ry = __builtin_amdgcn_readfirstlane(offy);
-            const bool uniform =
-                __ballot(!q.inside || (valid && offx == rx && offy == ry)) == ~0ull;
+            // (inside this branch only lanes in the frame are active, so a
+            // full ballot also means that all 64 lanes take part in the lane
+            // shifts: a shift from an inactive lane would read zero)
+            const bool uniform = __ballot(valid && offx == rx && offy == ry) == ~0ull;
             if (uniform) {
                 const int tx0 = q.x - static_cast<int>(threadIdx.x);
                 const uint32_t r0 = static_cast<uint32_t>(q.y - ry) * static_cast<uint32_t>(w);
