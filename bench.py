@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+FP64_VECTOR_PEAK_GFLOPS = 78600.0  # MI355X float64 vector peak (256 CUs x 2.4 GHz)
 CSRC = os.path.join(ROOT, "paper_2307_12607_amd", "csrc")
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("warp_common.h", "warp_forward.hip",
                                                "warp_backward.hip")]
@@ -184,6 +185,51 @@ class Workload:
                 "us": round(us, 2), "alg_bytes": 8 * n * h * w, "gbs": round(gbs, 1),
                 "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
+    def run_quality_and_chain(self, reps=5):
+        """Frame quality (MSE/PSNR/SSIM) of the N*K predicted frames against
+        the other buffer set's frames, and the K-step chained warp."""
+        import paper_2307_12607_amd as exw
+        torch = self.torch
+        n, c, h, w, k = self.shape
+        s0, s1 = self.sets[0], self.sets[1 % len(self.sets)]
+        for s in (s0, s1):
+            exw.exw_warp_forward_batched(s["src"], s["mv"], self.phases, s["out"], None, None)
+        pred = s0["out"].reshape(n * k, c, h, w)
+        truth = s1["out"].reshape(n * k, c, h, w)
+        nb = exw.exw_frame_quality_workspace_bytes(n * k, c, h, w)
+        ws = torch.empty(nb, dtype=torch.uint8, device=pred.device)
+        q = torch.empty((n * k, 3), dtype=torch.float64, device=pred.device)
+        chain = torch.empty((k, n, c, h, w), dtype=pred.dtype, device=pred.device)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps * 1e3
+
+        q_us = timed(lambda: exw.exw_frame_quality(pred, truth, q, ws))
+        ch_us = timed(lambda: exw.exw_warp_chain(s0["src"], s0["mv"], 0.25, k, chain))
+        # float64 operations of the SSIM filter per position and channel: 11 taps
+        # x (2 mul + 2 add + 3 fma) per staged row (76 rows per 66 outputs), 11 x 5
+        # fma vertically, ~20 for the index; an fma counts 2
+        positions = n * k * c * (h - 10) * (w - 10)
+        flops = positions * (11 * 10 * 76 / 66 + 11 * 5 * 2 + 20)
+        return ({"workload": f"config{self.spec.index}: MSE/PSNR/SSIM of {n * k} frames "
+                             f"{w}x{h} C={c} {self.dtype}",
+                 "us": round(q_us, 1), "bound": "alu",
+                 "fp64_gflop_s": round(flops / (q_us * 1e-6) / 1e9, 1),
+                 "peak_fp64_gflop_s": FP64_VECTOR_PEAK_GFLOPS,
+                 "frac": round(flops / (q_us * 1e-6) / 1e9 / FP64_VECTOR_PEAK_GFLOPS, 4)},
+                {"workload": f"config{self.spec.index}: {k} chained quarter-step warps "
+                             f"of {n}x{w}x{h} C={c} {self.dtype}",
+                 "us": round(ch_us, 1),
+                 "direct_fwd_phases_us": None})
+
     def free(self):
         self.sets = []
         self.torch.cuda.empty_cache()
@@ -267,6 +313,8 @@ def main():
     wl_name = main_wl.name()
     traffic = load_traffic(dominant, wl_name)
     stats_line = main_wl.run_motion_stats()
+    quality_line, chain_line = main_wl.run_quality_and_chain()
+    chain_line["direct_fwd_phases_us"] = round(r["fwd_ms"] * 1e3, 1)
     main_wl.free()
 
     variants = []
@@ -314,6 +362,8 @@ def main():
                       "copy_ceiling_gbs": round(ceiling, 1)},
         "variants": variants,
         "motion_stats": stats_line,
+        "frame_quality": quality_line,
+        "warp_chain": chain_line,
     }
     print(json.dumps(rec), flush=True)
 
