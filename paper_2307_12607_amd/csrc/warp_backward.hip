@@ -7,10 +7,10 @@
 // ns even fully coalesced, and each one is a write to memory, so the scatter
 // is turned into a gather instead:
 //
-//   pass 1 (footprint): one wavefront per 64-pixel row segment of the output
-//     reads the segment's motion and records the bounding box of all its
-//     taps over all phases, plus the per-frame largest distance between a
-//     segment and its box.
+//   pass 1 (footprint): for every 64-pixel row segment of the output, the
+//     bounding box of all its taps over all phases, plus the per-frame
+//     largest distance between a segment and its box (one wavefront per 16
+//     rows of a 64-pixel column; reads the motion once).
 //   pass 2 (tiles): one wavefront owns a 128 x TH tile of the image gradient
 //     in LDS. It walks the segments whose boxes reach the tile (only those
 //     within the per-frame distance can), recomputes their taps, accumulates

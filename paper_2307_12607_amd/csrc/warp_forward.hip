@@ -11,11 +11,13 @@
 // wavefronts per 64 x 4 tile, tiles renumbered per XCD. The motion vector is
 // read once for all K phases; motion, output and mask accesses are
 // coalesced; the taps of neighbouring lanes fall on neighbouring addresses
-// wherever the motion is locally smooth, and the two horizontal taps of a row
-// come in one (unaligned) 8-byte load. Measured HBM traffic equals the
-// algorithmic bytes (the L2 serves the overlap between tiles), so the taps
-// are gathered from global memory; an LDS-staged variant and a 4-pixels-per-
-// lane variant were both measured slower. No MFMA: this is a gather.
+// wherever the motion is locally smooth. In a wavefront whose lanes share one
+// integer tap offset, each row and channel is one aligned element load and a
+// lane shift; otherwise the two horizontal taps of a row come in one
+// (unaligned) 8-byte load. Measured HBM traffic equals the algorithmic bytes
+// (the L2 serves the overlap between tiles), so the taps are gathered from
+// global memory; an LDS-staged variant and a 4-pixels-per-lane variant were
+// both measured slower. No MFMA: this is a gather.
 #include "launch.h"
 #include "warp_common.h"
 
@@ -153,7 +155,8 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
 }
 
 // Channel count CT and phase count KT known at compile time; requires W >= 2
-// (paired horizontal loads). One phase at a time: its gathers, then its
+// (paired horizontal loads). Wavefronts that are uniform in every phase take
+// all_phases_uniform; the others go one phase at a time: its gathers, then its
 // stores. Addresses are 32-bit offsets inside a plane added to per-plane base
 // pointers that are uniform across the wavefront (scalar registers), which
 // keeps 64-bit address arithmetic off the vector ALU.
