@@ -27,9 +27,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 FP64_VECTOR_PEAK_GFLOPS = 78600.0  # MI355X float64 vector peak (256 CUs x 2.4 GHz)
-CSRC = os.path.join(ROOT, "paper_2307_12607_amd", "csrc")
-KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("warp_common.h", "warp_forward.hip",
-                                               "warp_backward.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
 
@@ -56,24 +53,48 @@ def algorithmic_bytes(n, c, h, w, k, b):
     return fwd, bwd
 
 
-def source_sha():
-    """Hash of the kernel sources: stored counter readings apply only to these."""
-    h = hashlib.sha256()
-    for path in KERNEL_SRCS:
-        with open(path, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def _elf_section(path, name):
+    """Bytes of one section of an ELF64 little-endian file (None if absent)."""
+    with open(path, "rb") as f:
+        data = f.read()
+    if data[:4] != b"\x7fELF" or data[4] != 2:
+        return None
+    u16 = lambda o: int.from_bytes(data[o:o + 2], "little")
+    u64 = lambda o: int.from_bytes(data[o:o + 8], "little")
+    shoff, shentsize, shnum, shstrndx = u64(0x28), u16(0x3A), u16(0x3C), u16(0x3E)
+    def header(i):
+        b = shoff + i * shentsize
+        return int.from_bytes(data[b:b + 4], "little"), u64(b + 0x18), u64(b + 0x20)
+    _, str_off, _ = header(shstrndx)
+    for i in range(shnum):
+        name_off, off, size = header(i)
+        end = data.index(b"\0", str_off + name_off)
+        if data[str_off + name_off:end].decode() == name:
+            return data[off:off + size]
+    return None
+
+
+def device_code_sha():
+    """Hash of the built library's device code (its .hip_fatbin section):
+    stored counter readings apply only to these kernels. Comments and host
+    code do not change it."""
+    import paper_2307_12607_amd._capi as capi
+    code = _elf_section(capi.LIB_PATH, ".hip_fatbin")
+    if code is None:
+        return None
+    return hashlib.sha256(code).hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):
     """HBM bytes per launch from stored rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+    taken on the current kernels (same device code); else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha") != source_sha():
+    sha = device_code_sha()
+    if sha is None or rec.get("device_code_sha") != sha:
         return None
     entry = rec.get("kernels", {}).get(f"{kernel}|{workload}")
     if not entry:
