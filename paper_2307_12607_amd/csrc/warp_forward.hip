@@ -37,6 +37,7 @@ struct FwdArgs {
     uint32_t *count;
     int n, c, h, w, k;
     int tiles_x, tiles_y;
+    int frame_32bit;  // C * H * W * sizeof(T) < 2^32: frame-relative 32-bit offsets
     float s[4];
 };
 
@@ -82,6 +83,11 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
                                                    float v, const T *img, int64_t hw,
                                                    uint32_t p) {
     const int w = a.w, h = a.h;
+    // Every access is the frame's wave-uniform base (scalar registers) plus a
+    // 32-bit offset channel * H*W + pixel: the caller checks that a frame of
+    // the source (and of one phase of the output) spans less than 4 GB.
+    const T *fin = img;
+    const uint32_t hw32 = static_cast<uint32_t>(hw);
     float fx[KT], fy[KT];
     int rx[KT], ry[KT];
     bool uni = true;
@@ -115,7 +121,7 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
         const int rowq = rq ? min(q.y - ryq + 1, h - 1) : q.y - ryq;
         const uint32_t off = static_cast<uint32_t>(rowq) * static_cast<uint32_t>(w) +
                              static_cast<uint32_t>(min(tx0 + kTileW - rxq, w - 1));
-        ex = to_f32(*at(img + cq * hw, off));
+        ex = to_f32(*at(fin, off + static_cast<uint32_t>(cq) * hw32));
     }
     float a0[KT][CT], a1[KT][CT];
 #pragma unroll
@@ -124,8 +130,8 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
         const uint32_t o0 = row0(j) + xa, o1 = row1(j) + xa;
 #pragma unroll
         for (int ch = 0; ch < CT; ++ch) {
-            a0[j][ch] = to_f32(*at(img + ch * hw, o0));
-            a1[j][ch] = to_f32(*at(img + ch * hw, o1));
+            a0[j][ch] = to_f32(*at(fin, o0 + ch * hw32));
+            a1[j][ch] = to_f32(*at(fin, o1 + ch * hw32));
         }
     }
 #pragma unroll
@@ -134,7 +140,7 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
         const float w01 = fx[j] * (1.0f - fy[j]);
         const float w10 = (1.0f - fx[j]) * fy[j];
         const float w11 = fx[j] * fy[j];
-        const int64_t plane = static_cast<int64_t>(q.in) * KT + j;
+        T *fout = a.out + (static_cast<int64_t>(q.in) * KT + j) * CT * hw;
 #pragma unroll
         for (int ch = 0; ch < CT; ++ch) {
             float b0 = shift_down1(a0[j][ch]), b1 = shift_down1(a1[j][ch]);
@@ -147,9 +153,9 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
             acc = fmaf(w01, b0, acc);
             acc = fmaf(w10, a1[j][ch], acc);
             acc = fmaf(w11, b1, acc);
-            *at(a.out + (plane * CT + ch) * hw, p) = from_f32<T>(acc);
+            *at(fout, p + ch * hw32) = from_f32<T>(acc);
         }
-        if (a.mask) *at(a.mask + plane * hw, p) = 1;  // every inside lane is valid
+        if (a.mask) *at(a.mask + (static_cast<int64_t>(q.in) * KT + j) * hw, p) = 1;  // all valid
     }
     return true;  // no invalid pixel: the zeroed counts stay as they are
 }
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
     // every wavefront): the gathers of all K phases are issued together, one
     // memory round trip instead of K.
     if constexpr (2 * CT * KT <= kTileW) {
-        if (all_phases_uniform<T, CT, KT>(a, q, u, v, img, hw, p)) return;
+        if (a.frame_32bit && all_phases_uniform<T, CT, KT>(a, q, u, v, img, hw, p)) return;
     }
 #pragma unroll 1
     for (int j = 0; j < KT; ++j) {
@@ -353,6 +359,7 @@ FwdArgs<T> make_args(const void *src, const float *mv, const WarpShape &s, void 
     a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
     a.tiles_x = (s.w + kTileW - 1) / kTileW;
     a.tiles_y = (s.h + kTileH - 1) / kTileH;
+    a.frame_32bit = static_cast<uint64_t>(s.c) * s.h * s.w * sizeof(T) < (uint64_t(1) << 32);
     for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
     return a;
 }
