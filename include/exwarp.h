@@ -114,10 +114,10 @@ exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t
                             void *stream);
 
 /* Bytes of device workspace exw_warp_backward_batched needs when grad_src is
- * requested: per-row-segment tap boxes (16 bytes per 64 output pixels of a
- * row), 8 bytes per frame, and for EXW_F16/EXW_BF16 a float32 image-gradient
- * accumulator of 4*N*C*H*W bytes. Returns 0 for an invalid dtype or an empty
- * batch. */
+ * requested: per row segment (64 output pixels of a row) a 16-byte tap box
+ * and 16 bytes of tap offsets, 8 bytes per frame, and for EXW_F16/EXW_BF16 a
+ * float32 image-gradient accumulator of 4*N*C*H*W bytes. Returns 0 for an
+ * invalid dtype or an empty batch. */
 size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                                          int32_t w);
 

@@ -8,9 +8,10 @@
 // is turned into a gather instead:
 //
 //   pass 1 (footprint): for every 64-pixel row segment of the output, the
-//     bounding box of all its taps over all phases, plus the per-frame
-//     largest distance between a segment and its box (one wavefront per 16
-//     rows of a 64-pixel column; reads the motion once).
+//     bounding box of all its taps over all phases, its integer tap offsets
+//     when every lane shares them ("uniform" segments: rigid motion), plus
+//     the per-frame largest distance between a segment and its box (one
+//     wavefront per 16 rows of a 64-pixel column; reads the motion once).
 //   pass 2 (tiles): one wavefront owns a 128 x TH tile of the image gradient
 //     in LDS. It walks the segments whose boxes reach the tile (only those
 //     within the per-frame distance can), recomputes their taps, accumulates
@@ -39,6 +40,15 @@ struct Box {
     int x_lo, x_hi, y_lo, y_hi;  // inclusive; x_lo > x_hi when the segment has no valid tap
 };
 
+// Integer tap offsets of a "uniform" segment: every lane is valid in every
+// phase and all 64 lanes share ceil(s_k * u) and ceil(s_k * v), packed per
+// phase k as (cx & 0xffff) | (cy << 16). Other segments hold kNotUniform in
+// word 0 (offsets of uniform segments lie in [-32767, 32767]).
+struct SegOffsets {
+    uint32_t k[4];
+};
+constexpr uint32_t kNotUniform = 0x80008000u;
+
 struct FrameInfo {
     int reach;    // largest distance (px) between a near segment and its box
     int has_far;  // 1 if a segment of this frame reaches further than kFar
@@ -53,6 +63,7 @@ struct BwdArgs {
     float *gmv;       // motion gradient, or NULL
     float *accum32;   // float32 accumulator for 16-bit frames with far segments
     Box *boxes;       // [N][H][segs]
+    SegOffsets *offs; // [N][H][segs]
     FrameInfo *info;  // [N]
     int n, c, h, w, k;
     int segs;         // segments per row
@@ -77,8 +88,9 @@ constexpr int kFootRows = 16;
 // loads are issued first, then the per-row boxes are reduced across lanes.
 template <int KT>
 __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Box *boxes,
-                                                             FrameInfo *info, int n, int h, int w,
-                                                             int segs, Phases4 ph) {
+                                                             SegOffsets *offs, FrameInfo *info,
+                                                             int n, int h, int w, int segs,
+                                                             Phases4 ph) {
     // The wavefront's unit index is made scalar so that its decoding runs on
     // the scalar unit; the unit count (one per 16 rows x 64 columns) is below
     // 2^31 (the C ABI bounds the count of 4 x 64 tiles of the same frames).
@@ -108,12 +120,18 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
     // Per lane, the smallest and largest first tap (x0 = x - ceil(d), the
     // exact floor of x - d) over the valid phases; the second tap is x0 + 1
     // clamped to the frame, applied once to the reduced maximum.
+    // Row r's segment offsets are collected in lane r (rec), which stores them.
     int xl[kFootRows], xh[kFootRows], yl[kFootRows], yh[kFootRows];
+    uint32_t rec[KT];
+#pragma unroll
+    for (int j = 0; j < KT; ++j) rec[j] = 0;
 #pragma unroll
     for (int r = 0; r < kFootRows; ++r) {
         const int y = y0 + r;
         const bool in_r = x < w && y < h;
         xl[r] = INT_MAX; xh[r] = INT_MIN; yl[r] = INT_MAX; yh[r] = INT_MIN;
+        bool uniform = true;  // wave-uniform
+        uint32_t packed[KT];
 #pragma unroll
         for (int j = 0; j < KT; ++j) {  // branch-free: invalid phases leave the box as is
             const float dx = ph.s[j] * u[r], dy = ph.s[j] * v[r];
@@ -121,12 +139,23 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
             const bool ok = in_r && dx <= static_cast<float>(x) &&
                             dx >= static_cast<float>(x - (w - 1)) &&
                             dy <= static_cast<float>(y) && dy >= static_cast<float>(y - (h - 1));
-            const int x0 = x - static_cast<int>(ceilf(ok ? dx : 0.0f));
-            const int y0t = y - static_cast<int>(ceilf(ok ? dy : 0.0f));
+            const int cx = static_cast<int>(ceilf(ok ? dx : 0.0f));
+            const int cy = static_cast<int>(ceilf(ok ? dy : 0.0f));
+            const int x0 = x - cx, y0t = y - cy;
             xl[r] = min(xl[r], ok ? x0 : INT_MAX);
             xh[r] = max(xh[r], ok ? x0 : INT_MIN);
             yl[r] = min(yl[r], ok ? y0t : INT_MAX);
             yh[r] = max(yh[r], ok ? y0t : INT_MIN);
+            const int rcx = __builtin_amdgcn_readfirstlane(cx);
+            const int rcy = __builtin_amdgcn_readfirstlane(cy);
+            uniform = uniform && __ballot(ok && cx == rcx && cy == rcy) == ~0ull &&
+                      static_cast<unsigned>(rcx + 32767) <= 65534u &&
+                      static_cast<unsigned>(rcy + 32767) <= 65534u;
+            packed[j] = (static_cast<uint32_t>(rcx) & 0xffffu) | (static_cast<uint32_t>(rcy) << 16);
+        }
+        if (lane == r) {
+#pragma unroll
+            for (int j = 0; j < KT; ++j) rec[j] = uniform ? packed[j] : (j == 0 ? kNotUniform : 0u);
         }
     }
     // Reduced boxes are wave-uniform: the reach and far tests run on scalars.
@@ -153,7 +182,12 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
 #pragma unroll
         for (int r = 1; r < kFootRows; ++r)
             if (lane == r) b = Box{bx[r][0], bx[r][1], bx[r][2], bx[r][3]};
-        boxes[(static_cast<int64_t>(in) * h + y0 + lane) * segs + sc] = b;
+        const int64_t at_seg = (static_cast<int64_t>(in) * h + y0 + lane) * segs + sc;
+        boxes[at_seg] = b;
+        SegOffsets o{{0u, 0u, 0u, 0u}};
+#pragma unroll
+        for (int j = 0; j < KT; ++j) o.k[j] = rec[j];
+        offs[at_seg] = o;
     }
     if (lane == 0) {
         if (far) atomicMax(&info[in].has_far, 1);
@@ -209,6 +243,26 @@ __device__ __forceinline__ float shift_up1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
+// Motion gradient of one phase of a uniform segment (every lane valid, taps at
+// the wave-uniform offset): the same sums as motion_grad_phase, with the
+// samples passed in (i00 = a0, i01 = b0, i10 = a1, i11 = b1 per channel).
+template <int CT>
+__device__ __forceinline__ void motion_grad_samples(const float (&a0)[CT], const float (&b0)[CT],
+                                                    const float (&a1)[CT], const float (&b1)[CT],
+                                                    float fx, float fy, const float *g, float s,
+                                                    float &gu, float &gv) {
+    float su = 0.0f, sv = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < CT; ++ch) {
+        const float dsx = fmaf(fy, b1[ch] - a1[ch], (1.0f - fy) * (b0[ch] - a0[ch]));
+        const float dsy = fmaf(fx, b1[ch] - b0[ch], (1.0f - fx) * (a1[ch] - a0[ch]));
+        su = fmaf(g[ch], dsx, su);
+        sv = fmaf(g[ch], dsy, sv);
+    }
+    gu = fmaf(-s, su, gu);
+    gv = fmaf(-s, sv, gv);
+}
+
 // Channels of one LDS cell: padded to a multiple of four (one 16-byte LDS
 // access per four channels) from three channels up.
 template <int CT>
@@ -258,19 +312,19 @@ __device__ __forceinline__ void cell_write(float *acc, int cell, const float (&v
 template <typename T, int CT, int KT>
 struct SegLoad {
     float u, v;
+    uint32_t off;      // word (lane & 3) of the segment's SegOffsets
     T g[KT][CT];
 };
 
 // One wavefront owns a kTileW x TH tile of the image gradient and keeps it in
-// LDS as cells of CP consecutive channels, followed by one scratch cell per
-// lane (rows TH.. of the cell array, never stored). No other wavefront touches
-// that LDS, so no barriers are needed.
+// LDS as cells of CP consecutive channels. No other wavefront touches that
+// LDS, so no barriers are needed.
 //
 // Work list: the segments whose boxes reach the tile (only rows and columns
 // within the per-frame reach can), plus the tile's own segments ("home"),
 // which are replayed even when their taps lie elsewhere because the home tile
 // computes their motion gradient. Box loads run one batch of 64 candidates
-// ahead; motion and upstream-gradient loads run one segment ahead.
+// ahead; motion, upstream-gradient and tap-offset loads run one segment ahead.
 //
 // Accumulation: for one segment and phase, the lanes whose integer tap offset
 // (x - x0, y - y0) equals that of the first lane with an in-tile tap
@@ -278,14 +332,22 @@ struct SegLoad {
 // land on lane j+1's left-hand cells. Each lane therefore adds, without
 // atomics, its own left taps plus its left neighbour's right taps to its cell
 // of the uniform pattern (one read-add-write of the whole cell per row); lane
-// 63 also adds its right taps one cell further. Lanes whose cell lies outside
-// the tile use their scratch cell, so the read-add-writes need no branches.
+// 63 also adds its right taps one cell further. The pattern's row is the same
+// for every lane, so a row outside the tile is skipped by the whole wavefront;
+// lanes whose column lies outside the tile read a cell but do not write it.
 // Lanes with another offset (motion boundaries, random motion) add their taps
 // with LDS atomics, which serialise per lane on this hardware; the uniform path
 // must carry the bulk of the work.
+//
+// Uniform segments (pass 1 found every lane valid with one offset per phase)
+// skip the per-lane split, the pattern search and the atomics, and gather the
+// samples of their motion gradient with aligned loads shared by the phases
+// whose offsets agree. The vector-memory pipeline, not the ALUs, bounds this
+// kernel on the pan-and-rectangle workloads, so load instructions are what
+// these paths save.
 template <typename T, int CT, int KT>
 __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
-    extern __shared__ __attribute__((aligned(16))) float acc[];  // [TH * kTileW + kSegW][CP]
+    extern __shared__ __attribute__((aligned(16))) float acc[];  // [TH * kTileW][CP]
     constexpr int CP = CellWidth<CT>::value;
     const int TH = a.tile_h;
     const int w = a.w, h = a.h;
@@ -306,7 +368,7 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     const int reach = min(fi.reach, kFar);
     const int ncells = TH * kTileW;
 
-    for (int i = lane; i < (ncells + kSegW) * CP / 4; i += kSegW)
+    for (int i = lane; i < ncells * CP / 4; i += kSegW)
         reinterpret_cast<f32x4 *>(acc)[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
     // Candidate segments: rows within `reach` of the tile, and columns whose
@@ -376,10 +438,49 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         const uint32_t pc = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + min(x, w - 1);
         d.u = *at(mu, pc);
         d.v = *at(mvv, pc);
+        // A vector load (lane j reads word j & 3), not a scalar one: scalar
+        // loads share their wait counter with LDS, and every LDS wait of the
+        // current replay would also wait for this prefetch.
+        const SegOffsets *so =
+            a.offs + (static_cast<int64_t>(in) * h + y) * a.segs + (sc_lo + (i & cm));
+        d.off = so->k[lane & 3];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
 #pragma unroll
             for (int ch = 0; ch < CT; ++ch) d.g[k][ch] = *at(gplane[k][ch], pc);
+    };
+
+    // Uniform-pattern accumulation of one phase: lane j adds its left taps and
+    // lane j-1's right taps to pattern cell (row uy0 / uy0 + 1, column ux);
+    // uy0 is wave-uniform, ux = ux(lane 0) + lane.
+    auto scatter_pattern = [&](int ux, int uy0, float fx, float fy, const float (&gg)[CT]) {
+        const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+        const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+        // Lanes whose column lies outside the tile read some cell of the row
+        // but do not write it back (the shift above needs every lane).
+        const bool cx = (unsigned)ux < (unsigned)kTileW;
+        const int col = cx ? ux : 0;
+        auto add_row = [&](int r, float wl, float wr) {
+            const int cell = r * kTileW + col;
+            float c[CP], right[CT];
+            cell_read<CP>(acc, cell, c);
+#pragma unroll
+            for (int ch = 0; ch < CT; ++ch) {
+                right[ch] = wr * gg[ch];
+                c[ch] = fmaf(wl, gg[ch], c[ch]) + shift_up1(right[ch]);
+            }
+            if (cx) cell_write<CP>(acc, cell, c);
+            // lane 63's right-hand taps, one cell to the right
+            if (lane == kSegW - 1 && (unsigned)(ux + 1) < (unsigned)kTileW) {
+                const int c1 = r * kTileW + ux + 1;
+                cell_read<CP>(acc, c1, c);
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) c[ch] += right[ch];
+                cell_write<CP>(acc, c1, c);
+            }
+        };
+        if ((unsigned)uy0 < (unsigned)TH) add_row(uy0, w00, w01);
+        if ((unsigned)(uy0 + 1) < (unsigned)TH) add_row(uy0 + 1, w10, w11);
     };
 
     // Replay of one segment (code from next_seg, loads from load_seg).
@@ -390,13 +491,34 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         const int sx0 = (sc_lo + (i & cm)) * kSegW;
         const int x = sx0 + lane;
         const bool inx = x < w;
+        // A uniform segment (every lane valid, one integer offset per phase,
+        // from pass 1) needs no per-lane validity or pattern tests.
+        const bool seg_uniform = __builtin_amdgcn_readlane(cur.off, 0) != kNotUniform;
         PTaps t[KT];
+        int ox[KT], oy[KT];  // the offsets of a uniform segment (wave-uniform)
         float g[KT][CT];
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            t[k].ax = split_axis(a.s[k] * cur.u, x, w);
-            t[k].ay = split_axis(a.s[k] * cur.v, y, h);
-            t[k].valid = inx && t[k].ax.ok && t[k].ay.ok;
+            const float dx = a.s[k] * cur.u, dy = a.s[k] * cur.v;
+            if (seg_uniform) {
+                const uint32_t o = __builtin_amdgcn_readlane(cur.off, k);
+                ox[k] = static_cast<int16_t>(o & 0xffffu);
+                oy[k] = static_cast<int>(o) >> 16;
+                // the split of an ok lane: i0 = p - ceil(d), f = ceil(d) - d
+                t[k].ax.i0 = x - ox[k];
+                t[k].ax.i1 = min(t[k].ax.i0 + 1, w - 1);
+                t[k].ax.f = static_cast<float>(ox[k]) - dx;
+                t[k].ax.ok = true;
+                t[k].ay.i0 = y - oy[k];
+                t[k].ay.i1 = min(t[k].ay.i0 + 1, h - 1);
+                t[k].ay.f = static_cast<float>(oy[k]) - dy;
+                t[k].ay.ok = true;
+                t[k].valid = true;
+            } else {
+                t[k].ax = split_axis(dx, x, w);
+                t[k].ay = split_axis(dy, y, h);
+                t[k].valid = inx && t[k].ax.ok && t[k].ay.ok;
+            }
 #pragma unroll
             for (int ch = 0; ch < CT; ++ch) g[k][ch] = to_f32(cur.g[k][ch]);
         }
@@ -404,9 +526,36 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         // Motion gradient of the home segments (every pixel written once).
         if (a.gmv && (unsigned)(y - ty0) < (unsigned)TH && sx0 / kTileW == tx) {
             float gu = 0.0f, gv = 0.0f;
+            if (seg_uniform) {
+                // The taps of a uniform segment are contiguous across lanes:
+                // aligned, coalesced single-element loads of the left and the
+                // right taps (the second load touches the same cache lines).
+                // Phases with the same offsets read the same pixels and share
+                // the loads.
+                float a0[CT], a1[CT], b0[CT], b1[CT];
 #pragma unroll
-            for (int k = 0; k < KT; ++k)
-                if (t[k].valid) motion_grad_phase<T, CT>(iplane, w, t[k], g[k], a.s[k], gu, gv);
+                for (int k = 0; k < KT; ++k) {
+                    if (k == 0 || ox[k] != ox[k - 1] || oy[k] != oy[k - 1]) {  // wave-uniform
+                        const uint32_t r0 = static_cast<uint32_t>(y - oy[k]) * static_cast<uint32_t>(w);
+                        const uint32_t r1 =
+                            static_cast<uint32_t>(min(y - oy[k] + 1, h - 1)) * static_cast<uint32_t>(w);
+                        const uint32_t xa = static_cast<uint32_t>(x - ox[k]);  // in the row
+                        const uint32_t xb = static_cast<uint32_t>(min(x - ox[k] + 1, w - 1));
+#pragma unroll
+                        for (int ch = 0; ch < CT; ++ch) {
+                            a0[ch] = to_f32(*at(iplane[ch], r0 + xa));
+                            b0[ch] = to_f32(*at(iplane[ch], r0 + xb));
+                            a1[ch] = to_f32(*at(iplane[ch], r1 + xa));
+                            b1[ch] = to_f32(*at(iplane[ch], r1 + xb));
+                        }
+                    }
+                    motion_grad_samples<CT>(a0, b0, a1, b1, t[k].ax.f, t[k].ay.f, g[k], a.s[k], gu, gv);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    if (t[k].valid) motion_grad_phase<T, CT>(iplane, w, t[k], g[k], a.s[k], gu, gv);
+            }
             if (inx) {
                 float *gm = a.gmv + 2 * static_cast<int64_t>(in) * hw;
                 const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + x;
@@ -415,85 +564,62 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
             }
         }
 
-        if (near) {  // wave-uniform; far segments are scattered by pass 3
+        if (!near) return;  // wave-uniform; far segments are scattered by pass 3
+        if (seg_uniform) {
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                // A tap lies in the tile iff the first tap is at most one
-                // column (row) before it: the second is the first + 1, or the
-                // same at the last column (row).
-                const int lx0 = t[k].ax.i0 - tx0, ly0 = t[k].ay.i0 - ty0;
-                const bool any = t[k].valid && (unsigned)(lx0 + 1) < (unsigned)(kTileW + 1) &&
-                                 (unsigned)(ly0 + 1) < (unsigned)(TH + 1);
-                const unsigned long long any_m = __ballot(any);
-                if (any_m == 0ull) continue;  // wave-uniform
-                // Uniform offset: that of the first lane with an in-tile tap.
-                const int offx = x - t[k].ax.i0, offy = y - t[k].ay.i0;
-                const int src_lane = __builtin_ctzll(any_m);
-                const int rx = __builtin_amdgcn_readlane(offx, src_lane);
-                const int ry = __builtin_amdgcn_readlane(offy, src_lane);
-                const bool uni = any && offx == rx && offy == ry;
-                const float fx = t[k].ax.f, fy = t[k].ay.f;
-                const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
-                const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
-                const int ux = x - rx - tx0;
-                const int uy0 = y - ry - ty0;
-                const bool cx = (unsigned)ux < (unsigned)kTileW;
-                const int scratch = ncells + lane;
-                const int c_top = cx && (unsigned)uy0 < (unsigned)TH ? uy0 * kTileW + ux : scratch;
-                const int c_bot =
-                    cx && (unsigned)(uy0 + 1) < (unsigned)TH ? (uy0 + 1) * kTileW + ux : scratch;
-                float c01[CP], c11[CP], rt[CP], rb[CP];
-                cell_read<CP>(acc, c_top, rt);
-                cell_read<CP>(acc, c_bot, rb);
-                // (lanes off the pattern take part with g = 0: their cell of
-                // the pattern still receives the left neighbour's taps)
+                // pattern column of lane 0 and pattern row (wave-uniform); the
+                // taps span columns ux0 .. ux0 + 64 and rows uy0, uy0 + 1
+                const int ux0 = sx0 - ox[k] - tx0, uy0 = y - oy[k] - ty0;
+                if (ux0 < -kSegW || ux0 >= kTileW || uy0 < -1 || uy0 >= TH) continue;
+                scatter_pattern(ux0 + lane, uy0, t[k].ax.f, t[k].ay.f, g[k]);
+            }
+            return;
+        }
 #pragma unroll
-                for (int ch = 0; ch < CT; ++ch) {
-                    const float gg = uni ? g[k][ch] : 0.0f;
-                    c01[ch] = w01 * gg;
-                    c11[ch] = w11 * gg;
-                    rt[ch] = fmaf(w00, gg, rt[ch]) + shift_up1(c01[ch]);
-                    rb[ch] = fmaf(w10, gg, rb[ch]) + shift_up1(c11[ch]);
-                }
-                cell_write<CP>(acc, c_top, rt);
-                cell_write<CP>(acc, c_bot, rb);
-                // lane 63's right-hand taps, one cell to the right
-                if (lane == kSegW - 1 && (unsigned)(ux + 1) < (unsigned)kTileW) {
-                    if ((unsigned)uy0 < (unsigned)TH) {
-                        const int c = uy0 * kTileW + ux + 1;
-                        cell_read<CP>(acc, c, rt);
+        for (int k = 0; k < KT; ++k) {
+            // A tap lies in the tile iff the first tap is at most one column
+            // (row) before it: the second is the first + 1, or the same at the
+            // last column (row).
+            const int lx0 = t[k].ax.i0 - tx0, ly0 = t[k].ay.i0 - ty0;
+            const bool any = t[k].valid && (unsigned)(lx0 + 1) < (unsigned)(kTileW + 1) &&
+                             (unsigned)(ly0 + 1) < (unsigned)(TH + 1);
+            const unsigned long long any_m = __ballot(any);
+            if (any_m == 0ull) continue;  // wave-uniform
+            // Uniform offset: that of the first lane with an in-tile tap.
+            const int offx = x - t[k].ax.i0, offy = y - t[k].ay.i0;
+            const int src_lane = __builtin_ctzll(any_m);
+            const int rx = __builtin_amdgcn_readlane(offx, src_lane);
+            const int ry = __builtin_amdgcn_readlane(offy, src_lane);
+            const bool uni = any && offx == rx && offy == ry;
+            // (lanes off the pattern take part with g = 0: their cell of the
+            // pattern still receives the left neighbour's taps)
+            float gg[CT];
 #pragma unroll
-                        for (int ch = 0; ch < CT; ++ch) rt[ch] += c01[ch];
-                        cell_write<CP>(acc, c, rt);
-                    }
-                    if ((unsigned)(uy0 + 1) < (unsigned)TH) {
-                        const int c = (uy0 + 1) * kTileW + ux + 1;
-                        cell_read<CP>(acc, c, rb);
+            for (int ch = 0; ch < CT; ++ch) gg[ch] = uni ? g[k][ch] : 0.0f;
+            const float fx = t[k].ax.f, fy = t[k].ay.f;
+            scatter_pattern(x - rx - tx0, y - ry - ty0, fx, fy, gg);
+            // Lanes off the uniform pattern (motion boundaries): LDS atomics.
+            if (__ballot(any && !uni)) {
+                if (any && !uni) {
+                    const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+                    const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+                    const int lx1 = t[k].ax.i1 - tx0, ly1 = t[k].ay.i1 - ty0;
+                    const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
+                    const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
+                    const bool iny0 = (unsigned)ly0 < (unsigned)TH;
+                    const bool iny1 = (unsigned)ly1 < (unsigned)TH;
 #pragma unroll
-                        for (int ch = 0; ch < CT; ++ch) rb[ch] += c11[ch];
-                        cell_write<CP>(acc, c, rb);
-                    }
-                }
-                // Lanes off the uniform pattern (motion boundaries): LDS atomics.
-                if (__ballot(any && !uni)) {
-                    if (any && !uni) {
-                        const int lx1 = t[k].ax.i1 - tx0, ly1 = t[k].ay.i1 - ty0;
-                        const bool inx0 = (unsigned)lx0 < (unsigned)kTileW;
-                        const bool inx1 = (unsigned)lx1 < (unsigned)kTileW;
-                        const bool iny0 = (unsigned)ly0 < (unsigned)TH;
-                        const bool iny1 = (unsigned)ly1 < (unsigned)TH;
-#pragma unroll
-                        for (int ch = 0; ch < CT; ++ch) {
-                            const float gg = g[k][ch];
-                            if (inx0 && iny0 && w00 != 0.0f)
-                                atomicAdd(acc + (ly0 * kTileW + lx0) * CP + ch, w00 * gg);
-                            if (inx1 && iny0 && w01 != 0.0f)
-                                atomicAdd(acc + (ly0 * kTileW + lx1) * CP + ch, w01 * gg);
-                            if (inx0 && iny1 && w10 != 0.0f)
-                                atomicAdd(acc + (ly1 * kTileW + lx0) * CP + ch, w10 * gg);
-                            if (inx1 && iny1 && w11 != 0.0f)
-                                atomicAdd(acc + (ly1 * kTileW + lx1) * CP + ch, w11 * gg);
-                        }
+                    for (int ch = 0; ch < CT; ++ch) {
+                        const float gk = g[k][ch];
+                        if (inx0 && iny0 && w00 != 0.0f)
+                            atomicAdd(acc + (ly0 * kTileW + lx0) * CP + ch, w00 * gk);
+                        if (inx1 && iny0 && w01 != 0.0f)
+                            atomicAdd(acc + (ly0 * kTileW + lx1) * CP + ch, w01 * gk);
+                        if (inx0 && iny1 && w10 != 0.0f)
+                            atomicAdd(acc + (ly1 * kTileW + lx0) * CP + ch, w10 * gk);
+                        if (inx1 && iny1 && w11 != 0.0f)
+                            atomicAdd(acc + (ly1 * kTileW + lx1) * CP + ch, w11 * gk);
                     }
                 }
             }
@@ -777,11 +903,10 @@ hipError_t run(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
     const unsigned foot_blocks =
         static_cast<unsigned>((foot_units + kThreads / kSegW - 1) / (kThreads / kSegW));
     hipLaunchKernelGGL((footprint_kernel<KT>), dim3(foot_blocks), dim3(kThreads), 0, st, a.mv,
-                       a.boxes, a.info, a.n, a.h, a.w, a.segs, ph);
+                       a.boxes, a.offs, a.info, a.n, a.h, a.w, a.segs, ph);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    // cells of the tile plus one scratch cell per lane
-    const size_t lds = sizeof(float) * CellWidth<CT>::value * (a.tile_h * kTileW + kSegW);
+    const size_t lds = sizeof(float) * CellWidth<CT>::value * a.tile_h * kTileW;
     const int64_t tiles = static_cast<int64_t>(a.n) * a.tiles_x * a.tiles_y;
     hipLaunchKernelGGL((adjoint_tiles_kernel<T, CT, KT>), dim3(static_cast<unsigned>(tiles)),
                        dim3(kSegW), lds, st, a);
@@ -821,6 +946,8 @@ hipError_t run_typed(const void *src, const float *mv, const WarpShape &s, const
     a.gmv = gmv;
     a.accum32 = ws.accum32;
     a.boxes = reinterpret_cast<Box *>(ws.boxes);
+    a.offs = reinterpret_cast<SegOffsets *>(a.boxes + static_cast<size_t>(s.n) * s.h *
+                                                          ((s.w + kSegW - 1) / kSegW));
     a.info = reinterpret_cast<FrameInfo *>(ws.info);
     a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
     a.segs = (s.w + kSegW - 1) / kSegW;
@@ -841,7 +968,8 @@ hipError_t run_typed(const void *src, const float *mv, const WarpShape &s, const
 }  // namespace
 
 size_t backward_box_bytes(int n, int h, int w) {
-    return sizeof(Box) * static_cast<size_t>(n) * h * ((w + kSegW - 1) / kSegW);
+    return (sizeof(Box) + sizeof(SegOffsets)) * static_cast<size_t>(n) * h *
+           ((w + kSegW - 1) / kSegW);
 }
 
 size_t backward_info_bytes(int n) { return sizeof(FrameInfo) * static_cast<size_t>(n); }

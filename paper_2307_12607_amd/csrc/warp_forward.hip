@@ -126,6 +126,15 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
     float a0[KT][CT], a1[KT][CT];
 #pragma unroll
     for (int j = 0; j < KT; ++j) {
+        if (j > 0 && rx[j] == rx[j - 1] && ry[j] == ry[j - 1]) {  // wave-uniform
+            // same integer offsets as the previous phase: the same pixels
+#pragma unroll
+            for (int ch = 0; ch < CT; ++ch) {
+                a0[j][ch] = a0[j - 1][ch];
+                a1[j][ch] = a1[j - 1][ch];
+            }
+            continue;
+        }
         const uint32_t xa = static_cast<uint32_t>(q.x - rx[j]);  // in the row: every lane is valid
         const uint32_t o0 = row0(j) + xa, o1 = row1(j) + xa;
 #pragma unroll

@@ -135,9 +135,10 @@ def test_empty_batches_and_no_requested_gradient_are_no_ops():
 
 def test_workspace_size():
     L = _capi.lib()
-    # boxes: 16 B per 64-pixel row segment; 8 B per frame; float32 accumulator for 16-bit storage
+    # per 64-pixel row segment a 16 B tap box and 16 B of tap offsets; 8 B per
+    # frame; float32 accumulator for 16-bit storage
     def expect(dtype, n, c, h, w):
-        boxes = 16 * n * h * ((w + 63) // 64)
+        boxes = 32 * n * h * ((w + 63) // 64)
         info = (boxes + 255) // 256 * 256
         accum = (info + 8 * n + 255) // 256 * 256
         return accum + (0 if dtype == 0 else 4 * n * c * h * w)
