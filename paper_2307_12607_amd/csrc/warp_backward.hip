@@ -68,6 +68,7 @@ struct BwdArgs {
     int n, c, h, w, k;
     int segs;         // segments per row
     int tile_h, tiles_x, tiles_y;
+    int frame_32bit;  // C * H * W * sizeof(T) < 2^32: frame-relative 32-bit offsets
     float s[4];
 };
 
@@ -241,26 +242,6 @@ __device__ __forceinline__ void motion_grad_phase(const T *const *iplane, int w,
 // source reads as zero, so it folds into the consuming add.
 __device__ __forceinline__ float shift_up1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-
-// Motion gradient of one phase of a uniform segment (every lane valid, taps at
-// the wave-uniform offset): the same sums as motion_grad_phase, with the
-// samples passed in (i00 = a0, i01 = b0, i10 = a1, i11 = b1 per channel).
-template <int CT>
-__device__ __forceinline__ void motion_grad_samples(const float (&a0)[CT], const float (&b0)[CT],
-                                                    const float (&a1)[CT], const float (&b1)[CT],
-                                                    float fx, float fy, const float *g, float s,
-                                                    float &gu, float &gv) {
-    float su = 0.0f, sv = 0.0f;
-#pragma unroll
-    for (int ch = 0; ch < CT; ++ch) {
-        const float dsx = fmaf(fy, b1[ch] - a1[ch], (1.0f - fy) * (b0[ch] - a0[ch]));
-        const float dsy = fmaf(fx, b1[ch] - b0[ch], (1.0f - fx) * (a1[ch] - a0[ch]));
-        su = fmaf(g[ch], dsx, su);
-        sv = fmaf(g[ch], dsy, sv);
-    }
-    gu = fmaf(-s, su, gu);
-    gv = fmaf(-s, sv, gv);
 }
 
 // Channels of one LDS cell: padded to a multiple of four (one 16-byte LDS
@@ -526,30 +507,69 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         // Motion gradient of the home segments (every pixel written once).
         if (a.gmv && (unsigned)(y - ty0) < (unsigned)TH && sx0 / kTileW == tx) {
             float gu = 0.0f, gv = 0.0f;
-            if (seg_uniform) {
+            if (seg_uniform && a.frame_32bit) {
                 // The taps of a uniform segment are contiguous across lanes:
                 // aligned, coalesced single-element loads of the left and the
                 // right taps (the second load touches the same cache lines).
-                // Phases with the same offsets read the same pixels and share
-                // the loads.
-                float a0[CT], a1[CT], b0[CT], b1[CT];
+                // When all phases share their offsets (rigid motion slower
+                // than one pixel per phase step) they read the same pixels:
+                // each channel is loaded once and feeds every phase.
+                bool same = true;
 #pragma unroll
-                for (int k = 0; k < KT; ++k) {
-                    if (k == 0 || ox[k] != ox[k - 1] || oy[k] != oy[k - 1]) {  // wave-uniform
-                        const uint32_t r0 = static_cast<uint32_t>(y - oy[k]) * static_cast<uint32_t>(w);
-                        const uint32_t r1 =
-                            static_cast<uint32_t>(min(y - oy[k] + 1, h - 1)) * static_cast<uint32_t>(w);
-                        const uint32_t xa = static_cast<uint32_t>(x - ox[k]);  // in the row
-                        const uint32_t xb = static_cast<uint32_t>(min(x - ox[k] + 1, w - 1));
+                for (int k = 1; k < KT; ++k) same = same && ox[k] == ox[0] && oy[k] == oy[0];
+                // frame-relative 32-bit element offsets from the frame's
+                // wave-uniform base (the frame spans less than 4 GB)
+                auto samples = [&](int k, int ch, float &a0, float &b0, float &a1, float &b1) {
+                    const uint32_t pl = static_cast<uint32_t>(ch) * static_cast<uint32_t>(hw);
+                    const uint32_t r0 =
+                        pl + static_cast<uint32_t>(y - oy[k]) * static_cast<uint32_t>(w);
+                    const uint32_t r1 =
+                        pl + static_cast<uint32_t>(min(y - oy[k] + 1, h - 1)) * static_cast<uint32_t>(w);
+                    const uint32_t xa = static_cast<uint32_t>(x - ox[k]);  // in the row
+                    const uint32_t xb = static_cast<uint32_t>(min(x - ox[k] + 1, w - 1));
+                    a0 = to_f32(*at(img, r0 + xa));
+                    b0 = to_f32(*at(img, r0 + xb));
+                    a1 = to_f32(*at(img, r1 + xa));
+                    b1 = to_f32(*at(img, r1 + xb));
+                };
+                // per-phase sums over channels, in channel order as in
+                // motion_grad_phase
+                float su[KT], sv[KT];
+#pragma unroll
+                for (int k = 0; k < KT; ++k) su[k] = sv[k] = 0.0f;
+                auto accumulate = [&](int k, int ch, float a0, float b0, float a1, float b1) {
+                    const float fx = t[k].ax.f, fy = t[k].ay.f;
+                    const float dsx = fmaf(fy, b1 - a1, (1.0f - fy) * (b0 - a0));
+                    const float dsy = fmaf(fx, b1 - b0, (1.0f - fx) * (a1 - a0));
+                    su[k] = fmaf(g[k][ch], dsx, su[k]);
+                    sv[k] = fmaf(g[k][ch], dsy, sv[k]);
+                };
+                if (same) {  // wave-uniform
+#pragma unroll
+                    for (int ch = 0; ch < CT; ++ch) {
+                        float a0, b0, a1, b1;
+                        samples(0, ch, a0, b0, a1, b1);
+#pragma unroll
+                        for (int k = 0; k < KT; ++k) accumulate(k, ch, a0, b0, a1, b1);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) {
 #pragma unroll
                         for (int ch = 0; ch < CT; ++ch) {
-                            a0[ch] = to_f32(*at(iplane[ch], r0 + xa));
-                            b0[ch] = to_f32(*at(iplane[ch], r0 + xb));
-                            a1[ch] = to_f32(*at(iplane[ch], r1 + xa));
-                            b1[ch] = to_f32(*at(iplane[ch], r1 + xb));
+                            float a0, b0, a1, b1;
+                            samples(k, ch, a0, b0, a1, b1);
+                            accumulate(k, ch, a0, b0, a1, b1);
                         }
+                        // one phase's samples in registers at a time
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    motion_grad_samples<CT>(a0, b0, a1, b1, t[k].ax.f, t[k].ay.f, g[k], a.s[k], gu, gv);
+                }
+                // sx = x - s*u, so d sx / d u = -s (and likewise for v)
+#pragma unroll
+                for (int k = 0; k < KT; ++k) {
+                    gu = fmaf(-a.s[k], su[k], gu);
+                    gv = fmaf(-a.s[k], sv[k], gv);
                 }
             } else {
 #pragma unroll
@@ -869,18 +889,14 @@ hipError_t run_generic(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T> constexpr int dtype_code() { return 2; }
-template <> constexpr int dtype_code<float>() { return 0; }
-template <> constexpr int dtype_code<_Float16>() { return 1; }
-
-int tile_rows_for(int c, int dtype) {
-    // One wavefront per 128 x TH tile of float32 accumulators (1 KB per
-    // channel and row pair). Taller tiles replay fewer segments (3.5 replays
-    // per segment at TH = 2, 2.9 at TH = 3, 2.5 at TH = 4 on workload 2) but
-    // hold more LDS per wavefront; measured on workload 2, TH = 3 is fastest
-    // for float32 frames with up to four channels and TH = 2 for 16-bit
-    // frames (TH = 4 and 128 x 1 were slower in both).
-    return (dtype == 0 && c <= 4) ? 3 : 2;
+int tile_rows_for(int c) {
+    // One wavefront per 128 x TH tile of float32 accumulators (2 KB per
+    // four-channel row). Taller tiles replay fewer segments (3.5 replays per
+    // segment at TH = 2, 2.9 at TH = 3, 2.5 at TH = 4 on workload 2) but hold
+    // more LDS per wavefront; measured on workload 2, TH = 3 is fastest for
+    // float32 and 16-bit frames with up to four channels (TH = 2 and TH = 4
+    // were slower in both).
+    return c <= 4 ? 3 : 2;
 }
 
 template <typename T, int CT, int KT>
@@ -951,9 +967,10 @@ hipError_t run_typed(const void *src, const float *mv, const WarpShape &s, const
     a.info = reinterpret_cast<FrameInfo *>(ws.info);
     a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
     a.segs = (s.w + kSegW - 1) / kSegW;
-    a.tile_h = tile_rows_for(s.c, dtype_code<T>());
+    a.tile_h = tile_rows_for(s.c);
     a.tiles_x = (s.w + kTileW - 1) / kTileW;
     a.tiles_y = (s.h + a.tile_h - 1) / a.tile_h;
+    a.frame_32bit = static_cast<uint64_t>(s.c) * s.h * s.w * sizeof(T) < (uint64_t(1) << 32);
     for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
     switch (s.c) {
     case 1: return run_k<T, 1>(a, ws, st);
