@@ -118,73 +118,77 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
         u[r] = in_r ? *at(mu, p) : 0.0f;
         v[r] = in_r ? *at(mvv, p) : 0.0f;
     }
-    // Per lane, the smallest and largest first tap (x0 = x - ceil(d), the
-    // exact floor of x - d) over the valid phases; the second tap is x0 + 1
-    // clamped to the frame, applied once to the reduced maximum.
-    // Row r's segment offsets are collected in lane r (rec), which stores them.
-    int xl[kFootRows], xh[kFootRows], yl[kFootRows], yh[kFootRows];
+    // Row r's box and offsets are collected in lane r, which stores them.
+    // A uniform row (every lane valid, one offset per phase) takes its box
+    // from the offsets on the scalar unit; other rows reduce it across lanes.
+    Box mine{1, 0, 1, 0};
     uint32_t rec[KT];
 #pragma unroll
     for (int j = 0; j < KT; ++j) rec[j] = 0;
+    int reach_max = -1, far = 0;  // wave-uniform
 #pragma unroll
     for (int r = 0; r < kFootRows; ++r) {
         const int y = y0 + r;
         const bool in_r = x < w && y < h;
-        xl[r] = INT_MAX; xh[r] = INT_MIN; yl[r] = INT_MAX; yh[r] = INT_MIN;
         bool uniform = true;  // wave-uniform
         uint32_t packed[KT];
+        bool okj[KT];
+        int cxj[KT], cyj[KT];
+        int cx_lo = INT_MAX, cx_hi = INT_MIN, cy_lo = INT_MAX, cy_hi = INT_MIN;
 #pragma unroll
-        for (int j = 0; j < KT; ++j) {  // branch-free: invalid phases leave the box as is
+        for (int j = 0; j < KT; ++j) {
             const float dx = ph.s[j] * u[r], dy = ph.s[j] * v[r];
             // the validity test of the warp: x - (w-1) <= dx <= x, likewise for y
-            const bool ok = in_r && dx <= static_cast<float>(x) &&
-                            dx >= static_cast<float>(x - (w - 1)) &&
-                            dy <= static_cast<float>(y) && dy >= static_cast<float>(y - (h - 1));
-            const int cx = static_cast<int>(ceilf(ok ? dx : 0.0f));
-            const int cy = static_cast<int>(ceilf(ok ? dy : 0.0f));
-            const int x0 = x - cx, y0t = y - cy;
-            xl[r] = min(xl[r], ok ? x0 : INT_MAX);
-            xh[r] = max(xh[r], ok ? x0 : INT_MIN);
-            yl[r] = min(yl[r], ok ? y0t : INT_MAX);
-            yh[r] = max(yh[r], ok ? y0t : INT_MIN);
-            const int rcx = __builtin_amdgcn_readfirstlane(cx);
-            const int rcy = __builtin_amdgcn_readfirstlane(cy);
-            uniform = uniform && __ballot(ok && cx == rcx && cy == rcy) == ~0ull &&
+            okj[j] = in_r && dx <= static_cast<float>(x) && dx >= static_cast<float>(x - (w - 1)) &&
+                     dy <= static_cast<float>(y) && dy >= static_cast<float>(y - (h - 1));
+            cxj[j] = static_cast<int>(ceilf(okj[j] ? dx : 0.0f));
+            cyj[j] = static_cast<int>(ceilf(okj[j] ? dy : 0.0f));
+            const int rcx = __builtin_amdgcn_readfirstlane(cxj[j]);
+            const int rcy = __builtin_amdgcn_readfirstlane(cyj[j]);
+            uniform = uniform && __ballot(okj[j] && cxj[j] == rcx && cyj[j] == rcy) == ~0ull &&
                       static_cast<unsigned>(rcx + 32767) <= 65534u &&
                       static_cast<unsigned>(rcy + 32767) <= 65534u;
             packed[j] = (static_cast<uint32_t>(rcx) & 0xffffu) | (static_cast<uint32_t>(rcy) << 16);
+            cx_lo = min(cx_lo, rcx); cx_hi = max(cx_hi, rcx);
+            cy_lo = min(cy_lo, rcy); cy_hi = max(cy_hi, rcy);
+        }
+        // first taps x0 = x - ceil(dx) (the exact floor of x - dx), y0 likewise
+        int b[4];
+        if (uniform) {
+            b[0] = sx0 - cx_hi; b[1] = sx0 + kSegW - 1 - cx_lo;
+            b[2] = y - cy_hi;   b[3] = y - cy_lo;
+        } else {  // branch-free per lane: invalid phases leave the box as is
+            int xl = INT_MAX, xh = INT_MIN, yl = INT_MAX, yh = INT_MIN;
+#pragma unroll
+            for (int j = 0; j < KT; ++j) {
+                xl = min(xl, okj[j] ? x - cxj[j] : INT_MAX);
+                xh = max(xh, okj[j] ? x - cxj[j] : INT_MIN);
+                yl = min(yl, okj[j] ? y - cyj[j] : INT_MAX);
+                yh = max(yh, okj[j] ? y - cyj[j] : INT_MIN);
+            }
+            b[0] = __builtin_amdgcn_readfirstlane(wave_min(xl));
+            b[1] = __builtin_amdgcn_readfirstlane(wave_max(xh));
+            b[2] = __builtin_amdgcn_readfirstlane(wave_min(yl));
+            b[3] = __builtin_amdgcn_readfirstlane(wave_max(yh));
+        }
+        if (b[0] > b[1] || y >= h) {
+            b[0] = 1; b[1] = 0; b[2] = 1; b[3] = 0;  // no valid tap
+        } else {
+            // the second tap is x0 + 1 clamped to the frame, applied to the maximum
+            b[1] = min(b[1] + 1, w - 1);
+            b[3] = min(b[3] + 1, h - 1);
+            const int rr = box_reach(Box{b[0], b[1], b[2], b[3]}, sx0, y);
+            if (rr > kFar) far = 1; else reach_max = max(reach_max, rr);
         }
         if (lane == r) {
+            mine = Box{b[0], b[1], b[2], b[3]};
 #pragma unroll
             for (int j = 0; j < KT; ++j) rec[j] = uniform ? packed[j] : (j == 0 ? kNotUniform : 0u);
         }
     }
-    // Reduced boxes are wave-uniform: the reach and far tests run on scalars.
-    int reach_max = -1, far = 0;
-    int bx[kFootRows][4];
-#pragma unroll
-    for (int r = 0; r < kFootRows; ++r) {
-        bx[r][0] = __builtin_amdgcn_readfirstlane(wave_min(xl[r]));
-        bx[r][1] = __builtin_amdgcn_readfirstlane(wave_max(xh[r]));
-        bx[r][2] = __builtin_amdgcn_readfirstlane(wave_min(yl[r]));
-        bx[r][3] = __builtin_amdgcn_readfirstlane(wave_max(yh[r]));
-        if (bx[r][0] > bx[r][1] || y0 + r >= h) {
-            bx[r][0] = 1; bx[r][1] = 0; bx[r][2] = 1; bx[r][3] = 0;  // no valid tap
-        } else {
-            bx[r][1] = min(bx[r][1] + 1, w - 1);
-            bx[r][3] = min(bx[r][3] + 1, h - 1);
-            const int rr = box_reach(Box{bx[r][0], bx[r][1], bx[r][2], bx[r][3]}, sx0, y0 + r);
-            if (rr > kFar) far = 1; else reach_max = max(reach_max, rr);
-        }
-    }
     if (lane < kFootRows && y0 + lane < h) {
-        // lane r stores row r's box (selected without dynamic register indexing)
-        Box b{bx[0][0], bx[0][1], bx[0][2], bx[0][3]};
-#pragma unroll
-        for (int r = 1; r < kFootRows; ++r)
-            if (lane == r) b = Box{bx[r][0], bx[r][1], bx[r][2], bx[r][3]};
         const int64_t at_seg = (static_cast<int64_t>(in) * h + y0 + lane) * segs + sc;
-        boxes[at_seg] = b;
+        boxes[at_seg] = mine;
         SegOffsets o{{0u, 0u, 0u, 0u}};
 #pragma unroll
         for (int j = 0; j < KT; ++j) o.k[j] = rec[j];
