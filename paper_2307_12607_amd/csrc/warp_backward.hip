@@ -549,10 +549,31 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                     sv[k] = fmaf(g[k][ch], dsy, sv[k]);
                 };
                 if (same) {  // wave-uniform
+                    // Lane j's right taps are lane j+1's left taps (a DPP
+                    // shift); lane 63's come from one load spread over lanes
+                    // 0 .. 2C-1 (row r0 for lanes < C, r1 above).
+                    const uint32_t r0 = static_cast<uint32_t>(y - oy[0]) * static_cast<uint32_t>(w);
+                    const uint32_t r1 =
+                        static_cast<uint32_t>(min(y - oy[0] + 1, h - 1)) * static_cast<uint32_t>(w);
+                    const uint32_t xa = static_cast<uint32_t>(x - ox[0]);  // in the row
+                    float ex = 0.0f;
+                    if (lane < 2 * CT) {
+                        const uint32_t cq = static_cast<uint32_t>(lane % CT);
+                        const uint32_t xe = static_cast<uint32_t>(min(sx0 + kSegW - ox[0], w - 1));
+                        ex = to_f32(*at(img, cq * static_cast<uint32_t>(hw) + (lane < CT ? r0 : r1) + xe));
+                    }
 #pragma unroll
                     for (int ch = 0; ch < CT; ++ch) {
-                        float a0, b0, a1, b1;
-                        samples(0, ch, a0, b0, a1, b1);
+                        const uint32_t pl = static_cast<uint32_t>(ch) * static_cast<uint32_t>(hw);
+                        const float a0 = to_f32(*at(img, pl + r0 + xa));
+                        const float a1 = to_f32(*at(img, pl + r1 + xa));
+                        const int e0 = __builtin_amdgcn_readlane(__float_as_int(ex), ch);
+                        const int e1 = __builtin_amdgcn_readlane(__float_as_int(ex), CT + ch);
+                        // wave shift left by one; lane 63 keeps the old value
+                        const float b0 = __int_as_float(
+                            __builtin_amdgcn_update_dpp(e0, __float_as_int(a0), 0x130, 0xf, 0xf, false));
+                        const float b1 = __int_as_float(
+                            __builtin_amdgcn_update_dpp(e1, __float_as_int(a1), 0x130, 0xf, 0xf, false));
 #pragma unroll
                         for (int k = 0; k < KT; ++k) accumulate(k, ch, a0, b0, a1, b1);
                     }
