@@ -37,7 +37,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
     p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    p.add_argument("--no-variants", action="store_true", help="skip the FP16 / 4K lines")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the other workloads (FP16, 4K, loss-gradient, G-buffer lines)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 1 GiB device copy first (for counter scaling)")
@@ -342,7 +343,10 @@ def main():
     if not args.no_variants:
         todo = [(args.config, "f16" if args.dtype == "f32" else "f32")]
         if args.config == 2:
-            todo += [(3, "f32"), (3, "f16")]
+            # 4K RGBA; 8 x 1080p RGB with s = 1 (the loss-gradient workload: the
+            # upstream gradient is a precomputed tensor, the loss is not timed);
+            # 4 x 1440p 12-channel G-buffers in bf16 and f32 storage
+            todo += [(3, "f32"), (3, "f16"), (4, "f32"), (5, "bf16"), (5, "f32")]
         for idx, dt in todo:
             wl = Workload(idx, dt, dev)
             vr = wl.run(max(5, args.steps // 3), 2)
