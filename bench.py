@@ -171,13 +171,21 @@ class Workload:
             step(warmup + i, evs[i])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        fwd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-        bwd_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+        fwd_each = sorted(e[0].elapsed_time(e[1]) for e in evs)
+        bwd_each = sorted(e[1].elapsed_time(e[2]) for e in evs)
+        fwd_ms = sum(fwd_each) / steps
+        bwd_ms = sum(bwd_each) / steps
         ms = 1e3 * elapsed / steps
+
+        def spread(xs):  # median, min, max of the per-step event times (ms)
+            return [round(xs[len(xs) // 2], 4), round(xs[0], 4), round(xs[-1], 4)]
+
         return {
             "ms_per_step": ms,
             "fwd_ms": fwd_ms,
             "bwd_ms": bwd_ms,
+            "fwd_ms_median_min_max": spread(fwd_each),
+            "bwd_ms_median_min_max": spread(bwd_each),
             "mpix_s": self.out_px / (ms * 1e-3) / 1e6,
             "fwd_mpix_s": self.out_px / (fwd_ms * 1e-3) / 1e6,
             "fwd_gbs": self.fwd_bytes / (fwd_ms * 1e-3) / 1e9,
@@ -353,6 +361,8 @@ def main():
             variants.append({"workload": wl.name(), "fwd_bwd_mpix_s": round(vr["mpix_s"], 1),
                              "fwd_mpix_s": round(vr["fwd_mpix_s"], 1),
                              "fwd_ms": round(vr["fwd_ms"], 4), "bwd_ms": round(vr["bwd_ms"], 4),
+                             "fwd_ms_median_min_max": vr["fwd_ms_median_min_max"],
+                             "bwd_ms_median_min_max": vr["bwd_ms_median_min_max"],
                              "fwd_hbm_frac": round(vr["fwd_gbs"] / HBM_PEAK_GBS, 4),
                              "bwd_hbm_frac": round(vr["bwd_gbs"] / HBM_PEAK_GBS, 4)})
             wl.free()
@@ -381,6 +391,8 @@ def main():
                      "traffic": traffic},
         "cpu_baseline": cpu,
         "breakdown": {"fwd_ms": round(r["fwd_ms"], 4), "bwd_ms": round(r["bwd_ms"], 4),
+                      "fwd_ms_median_min_max": r["fwd_ms_median_min_max"],
+                      "bwd_ms_median_min_max": r["bwd_ms_median_min_max"],
                       "fwd_mpix_s": round(r["fwd_mpix_s"], 1),
                       "fwd_gbs": round(r["fwd_gbs"], 1), "bwd_gbs": round(r["bwd_gbs"], 1),
                       "fwd_alg_bytes": main_wl.fwd_bytes, "bwd_alg_bytes": main_wl.bwd_bytes,
