@@ -442,7 +442,8 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
         const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
         // Lanes whose column lies outside the tile read some cell of the row
-        // but do not write it back (the shift above needs every lane).
+        // but do not write it back (the lane shift in the sums below needs
+        // every lane active).
         const bool cx = (unsigned)ux < (unsigned)kTileW;
         const int col = cx ? ux : 0;
         auto add_row = [&](int r, float wl, float wr) {
@@ -512,12 +513,14 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
         if (a.gmv && (unsigned)(y - ty0) < (unsigned)TH && sx0 / kTileW == tx) {
             float gu = 0.0f, gv = 0.0f;
             if (seg_uniform && a.frame_32bit) {
-                // The taps of a uniform segment are contiguous across lanes:
-                // aligned, coalesced single-element loads of the left and the
-                // right taps (the second load touches the same cache lines).
+                // The taps of a uniform segment are contiguous across lanes,
+                // so its samples are aligned, coalesced single-element loads.
                 // When all phases share their offsets (rigid motion slower
                 // than one pixel per phase step) they read the same pixels:
-                // each channel is loaded once and feeds every phase.
+                // each channel is loaded once, the right taps come from the
+                // neighbouring lane and the samples feed every phase.
+                // Otherwise each phase loads its left and its right taps (the
+                // second load touches the same cache lines).
                 bool same = true;
 #pragma unroll
                 for (int k = 1; k < KT; ++k) same = same && ox[k] == ox[0] && oy[k] == oy[0];
