@@ -24,9 +24,10 @@
 namespace exw {
 namespace {
 
-constexpr int kTileW = 64;
+constexpr int kTileW = 64;     // pixels of a row per wavefront in the one-pixel paths
 constexpr int kTileH = 4;
 constexpr int kThreads = kTileW * kTileH;
+constexpr int kSegPair = 2 * kTileW;  // pixels of a row per wavefront (two per lane)
 
 template <typename T>
 struct FwdArgs {
@@ -46,17 +47,6 @@ struct PixelPos {
     bool inside;
 };
 
-__device__ __forceinline__ PixelPos decode_pixel(int tiles_x, int tiles_y, int w, int h) {
-    const int b = xcd_tile_index(blockIdx.x, gridDim.x);
-    const int tx = b % tiles_x;
-    const int rest = b / tiles_x;
-    PixelPos q;
-    q.in = rest / tiles_y;
-    q.x = tx * kTileW + threadIdx.x;
-    q.y = (rest % tiles_y) * kTileH + threadIdx.y;
-    q.inside = (q.x < w) && (q.y < h);
-    return q;
-}
 
 // v from lane + 1 (0 into lane 63): a DPP wavefront shift.
 __device__ __forceinline__ float shift_down1(float v) {
@@ -176,9 +166,8 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
 // pointers that are uniform across the wavefront (scalar registers), which
 // keeps 64-bit address arithmetic off the vector ALU.
 template <typename T, int CT, int KT>
-__global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
+__device__ __forceinline__ void forward_row(const FwdArgs<T> &a, const PixelPos q) {
     const int w = a.w, h = a.h;
-    const PixelPos q = decode_pixel(a.tiles_x, a.tiles_y, w, h);
     const int64_t hw = static_cast<int64_t>(h) * w;
     const uint32_t p = static_cast<uint32_t>(q.y) * static_cast<uint32_t>(w) +
                        static_cast<uint32_t>(q.x);
@@ -305,12 +294,164 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
     }
 }
 
+// The wavefront's row, frame and 128-pixel segment; its first 64 pixels are
+// lanes 0..63 of half 0, the next 64 those of half 1.
+struct SegPos {
+    int in, y, sx0;
+};
+
+__device__ __forceinline__ SegPos decode_segment(int tiles_x, int tiles_y) {
+    const int b = xcd_tile_index(blockIdx.x, gridDim.x);
+    const int tx = b % tiles_x;
+    const int rest = b / tiles_x;
+    // (each wavefront is one threadIdx.y: the values are wave-uniform, and
+    // taking them from lane 0 keeps them, and the frame bases, in scalar
+    // registers)
+    SegPos g;
+    g.in = __builtin_amdgcn_readfirstlane(rest / tiles_y);
+    g.y = __builtin_amdgcn_readfirstlane((rest % tiles_y) * kTileH + static_cast<int>(threadIdx.y));
+    g.sx0 = __builtin_amdgcn_readfirstlane(tx * kSegPair);
+    return g;
+}
+
+__device__ __forceinline__ PixelPos half_pixel(const SegPos &g, int half, int w, int h) {
+    PixelPos q;
+    q.in = g.in;
+    q.x = g.sx0 + half * kTileW + threadIdx.x;
+    q.y = g.y;
+    q.inside = (q.x < w) && (q.y < h);
+    return q;
+}
+
+// Two adjacent stored values written at once (element-aligned address).
+typedef float f32x2_st __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32_st __attribute__((aligned(2)));
+typedef uint16_t u16_st __attribute__((aligned(1)));
+
+__device__ __forceinline__ void store_pair(float *p, float a, float b) {
+    f32x2_st v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<f32x2_st *>(p) = v;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pair(T *p, float a, float b) {
+    const T ta = from_f32<T>(a), tb = from_f32<T>(b);
+    uint16_t ba, bb;
+    __builtin_memcpy(&ba, &ta, 2);
+    __builtin_memcpy(&bb, &tb, 2);
+    *reinterpret_cast<u32_st *>(p) = static_cast<uint32_t>(ba) | (static_cast<uint32_t>(bb) << 16);
+}
+
+// Two pixels per lane: lane j owns pixels 2j and 2j+1 of the wavefront's
+// 128-pixel row segment. When every pixel is in the frame and each phase has
+// one integer tap offset for the whole segment, the pair's taps in a row are
+// columns c, c+1, c+2 (c = 2j minus the offset): one two-element load gives
+// c and c+1, lane j+1's first element is c+2 (a DPP shift; lane 63's come
+// from one load spread over lanes 0 .. 2C-1), and both outputs of a plane are
+// stored at once - half the memory instructions per pixel of the one-pixel
+// path. Phases with the offsets of the previous phase reuse its samples. The
+// blend is that of the one-pixel path, term for term. Returns false, having
+// written nothing, when the segment is not uniform.
+template <typename T, int CT, int KT>
+__device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &g) {
+    const int w = a.w, h = a.h, y = g.y;
+    const int64_t hw = static_cast<int64_t>(h) * w;
+    const uint32_t hw32 = static_cast<uint32_t>(hw);  // the frame spans less than 4 GB
+    const int x = g.sx0 + 2 * static_cast<int>(threadIdx.x);
+    const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + static_cast<uint32_t>(x);
+    const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
+    float u0, u1, v0, v1;
+    load_pair(at(mu, p), u0, u1);
+    load_pair(at(mu + hw, p), v0, v1);
+    float fx0[KT], fx1[KT], fy0[KT], fy1[KT];
+    int rx[KT], ry[KT];
+    bool uni = true;
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        const Axis ax0 = split_axis(a.s[j] * u0, x, w), ax1 = split_axis(a.s[j] * u1, x + 1, w);
+        const Axis ay0 = split_axis(a.s[j] * v0, y, h), ay1 = split_axis(a.s[j] * v1, y, h);
+        const int ox0 = x - ax0.i0, ox1 = x + 1 - ax1.i0;
+        const int oy0 = y - ay0.i0, oy1 = y - ay1.i0;
+        rx[j] = __builtin_amdgcn_readfirstlane(ox0);
+        ry[j] = __builtin_amdgcn_readfirstlane(oy0);
+        uni = uni && ax0.ok && ax1.ok && ay0.ok && ay1.ok && ox0 == rx[j] && ox1 == rx[j] &&
+              oy0 == ry[j] && oy1 == ry[j];
+        fx0[j] = ax0.f; fx1[j] = ax1.f;
+        fy0[j] = ay0.f; fy1[j] = ay1.f;
+    }
+    if (__ballot(uni) != ~0ull) return false;
+    const T *fin = a.src + static_cast<int64_t>(g.in) * CT * hw;
+    float s0[CT], t0[CT], s1[CT], t1[CT];  // columns c, c+1 of rows r0 and r1
+    float ex = 0.0f;                       // lane 63's column c+2, lanes 0 .. 2C-1
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+        if (j == 0 || rx[j] != rx[j - 1] || ry[j] != ry[j - 1]) {  // wave-uniform
+            const uint32_t r0 = static_cast<uint32_t>(y - ry[j]) * static_cast<uint32_t>(w);
+            const uint32_t r1 =
+                static_cast<uint32_t>(min(y - ry[j] + 1, h - 1)) * static_cast<uint32_t>(w);
+            const uint32_t c = static_cast<uint32_t>(x - rx[j]);  // in the row
+            if (threadIdx.x < 2 * CT) {
+                const uint32_t cq = threadIdx.x % CT;
+                const uint32_t ce = static_cast<uint32_t>(min(g.sx0 + kSegPair - rx[j], w - 1));
+                ex = to_f32(*at(fin, cq * hw32 + (threadIdx.x < CT ? r0 : r1) + ce));
+            }
+#pragma unroll
+            for (int ch = 0; ch < CT; ++ch) {
+                load_pair(at(fin, ch * hw32 + r0 + c), s0[ch], t0[ch]);
+                load_pair(at(fin, ch * hw32 + r1 + c), s1[ch], t1[ch]);
+            }
+        }
+        // pixel 2j: taps (s, t); pixel 2j+1: taps (t, next lane's s)
+        const float a00 = (1.0f - fx0[j]) * (1.0f - fy0[j]), a01 = fx0[j] * (1.0f - fy0[j]);
+        const float a10 = (1.0f - fx0[j]) * fy0[j], a11 = fx0[j] * fy0[j];
+        const float b00 = (1.0f - fx1[j]) * (1.0f - fy1[j]), b01 = fx1[j] * (1.0f - fy1[j]);
+        const float b10 = (1.0f - fx1[j]) * fy1[j], b11 = fx1[j] * fy1[j];
+        T *fout = a.out + (static_cast<int64_t>(g.in) * KT + j) * CT * hw;
+#pragma unroll
+        for (int ch = 0; ch < CT; ++ch) {
+            float n0 = shift_down1(s0[ch]), n1 = shift_down1(s1[ch]);
+            if (threadIdx.x == kTileW - 1) {
+                n0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), ch));
+                n1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), CT + ch));
+            }
+            float acc0 = a00 * s0[ch];
+            acc0 = fmaf(a01, t0[ch], acc0);
+            acc0 = fmaf(a10, s1[ch], acc0);
+            acc0 = fmaf(a11, t1[ch], acc0);
+            float acc1 = b00 * t0[ch];
+            acc1 = fmaf(b01, n0, acc1);
+            acc1 = fmaf(b10, t1[ch], acc1);
+            acc1 = fmaf(b11, n1, acc1);
+            store_pair(at(fout, p + ch * hw32), acc0, acc1);
+        }
+        if (a.mask)  // every pixel valid
+            *reinterpret_cast<u16_st *>(a.mask + (static_cast<int64_t>(g.in) * KT + j) * hw + p) = 0x0101;
+    }
+    return true;  // no invalid pixel: the zeroed counts stay as they are
+}
+
+// One 128-pixel row segment per wavefront: two pixels per lane when the whole
+// segment is uniform in every phase, otherwise the one-pixel paths on each
+// half.
+template <typename T, int CT, int KT>
+__global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
+    const SegPos g = decode_segment(a.tiles_x, a.tiles_y);
+    if constexpr (2 * CT * KT <= kTileW) {
+        if (a.frame_32bit && g.y < a.h && g.sx0 + kSegPair <= a.w &&  // wave-uniform
+            pair_uniform<T, CT, KT>(a, g))
+            return;
+    }
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) forward_row<T, CT, KT>(a, half_pixel(g, half, a.w, a.h));
+}
+
 // Any channel count, any phase count, any width (including W == 1): one
 // channel at a time, scalar taps.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void warp_forward_generic_kernel(FwdArgs<T> a) {
+__device__ __forceinline__ void generic_row(const FwdArgs<T> &a, const PixelPos q) {
     const int C = a.c, w = a.w, h = a.h;
-    const PixelPos q = decode_pixel(a.tiles_x, a.tiles_y, w, h);
     const int64_t hw = static_cast<int64_t>(h) * w;
     const int64_t p = static_cast<int64_t>(q.y) * w + q.x;
     float u = 0.0f, v = 0.0f;
@@ -349,6 +490,13 @@ __global__ __launch_bounds__(kThreads) void warp_forward_generic_kernel(FwdArgs<
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kThreads) void warp_forward_generic_kernel(FwdArgs<T> a) {
+    const SegPos g = decode_segment(a.tiles_x, a.tiles_y);
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) generic_row<T>(a, half_pixel(g, half, a.w, a.h));
+}
+
 __global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
@@ -366,7 +514,7 @@ FwdArgs<T> make_args(const void *src, const float *mv, const WarpShape &s, void 
     a.mask = mask;
     a.count = count;
     a.n = s.n; a.c = s.c; a.h = s.h; a.w = s.w; a.k = s.k;
-    a.tiles_x = (s.w + kTileW - 1) / kTileW;
+    a.tiles_x = (s.w + kSegPair - 1) / kSegPair;
     a.tiles_y = (s.h + kTileH - 1) / kTileH;
     a.frame_32bit = static_cast<uint64_t>(s.c) * s.h * s.w * sizeof(T) < (uint64_t(1) << 32);
     for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
