@@ -7,17 +7,20 @@
 // taps of every channel, and writes K output pixels, K mask bytes and the
 // per-(frame, phase) invalid counts.
 //
-// Layout of the work: a wavefront per 64 consecutive pixels of a row, four
-// wavefronts per 64 x 4 tile, tiles renumbered per XCD. The motion vector is
+// Layout of the work: a wavefront per 128 consecutive pixels of a row, four
+// wavefronts per 128 x 4 tile, tiles renumbered per XCD. The motion vector is
 // read once for all K phases; motion, output and mask accesses are
 // coalesced; the taps of neighbouring lanes fall on neighbouring addresses
-// wherever the motion is locally smooth. In a wavefront whose lanes share one
-// integer tap offset, each row and channel is one aligned element load and a
-// lane shift; otherwise the two horizontal taps of a row come in one
-// (unaligned) 8-byte load. Measured HBM traffic equals the algorithmic bytes
-// (the L2 serves the overlap between tiles), so the taps are gathered from
-// global memory; an LDS-staged variant and a 4-pixels-per-lane variant were
-// both measured slower. No MFMA: this is a gather.
+// wherever the motion is locally smooth. A segment whose 128 pixels share one
+// integer tap offset per phase takes two pixels per lane (two-element loads
+// and stores plus a lane shift); otherwise each 64-pixel half runs the
+// one-pixel paths: a wavefront whose lanes share one offset loads one aligned
+// element per row and channel plus a lane shift, others load the two
+// horizontal taps of a row in one (unaligned) 8-byte load. Measured HBM
+// traffic equals the algorithmic bytes (the L2 serves the overlap between
+// tiles), so the taps are gathered from global memory; an LDS-staged variant
+// and four pixels per lane were both measured slower. No MFMA: this is a
+// gather.
 #include "launch.h"
 #include "warp_common.h"
 
