@@ -308,8 +308,9 @@ struct SegLoad {
 // Work list: the segments whose boxes reach the tile (only rows and columns
 // within the per-frame reach can), plus the tile's own segments ("home"),
 // which are replayed even when their taps lie elsewhere because the home tile
-// computes their motion gradient. Box loads run one batch of 64 candidates
-// ahead; motion, upstream-gradient and tap-offset loads run one segment ahead.
+// computes their motion gradient. Candidates are classified 64 at a time from
+// their boxes; motion, upstream-gradient and tap-offset loads run one segment
+// ahead.
 //
 // Accumulation: for one segment and phase, the lanes whose integer tap offset
 // (x - x0, y - y0) equals that of the first lane with an in-tile tap
@@ -389,17 +390,17 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
     };
 
     int base = 0;
-    Box nb = box_of(lane);
     unsigned long long m_hit = 0, m_near = 0;
-    // Next segment to replay as (candidate << 1) | near, or -1 when done.
+    // Next segment to replay as (candidate << 1) | near, or -1 when done. A
+    // batch's boxes are loaded when it is classified: holding the next batch's
+    // boxes through the replays would cost four registers per lane all along.
     auto next_seg = [&]() -> int {
         while (m_hit == 0) {
             if (base >= total) return -1;
-            const int cls = classify(nb, base + lane);
+            const int cls = classify(box_of(base + lane), base + lane);
             m_hit = __ballot(cls != 0);
             m_near = __ballot(cls & 1);
             base += kSegW;
-            if (base < total) nb = box_of(base + lane);
         }
         const int j = __builtin_ctzll(m_hit);
         m_hit &= m_hit - 1;
@@ -559,12 +560,13 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
                     const uint32_t r1 =
                         static_cast<uint32_t>(min(y - oy[0] + 1, h - 1)) * static_cast<uint32_t>(w);
                     const uint32_t xa = static_cast<uint32_t>(x - ox[0]);  // in the row
-                    float ex = 0.0f;
-                    if (lane < 2 * CT) {
-                        const uint32_t cq = static_cast<uint32_t>(lane % CT);
-                        const uint32_t xe = static_cast<uint32_t>(min(sx0 + kSegW - ox[0], w - 1));
-                        ex = to_f32(*at(img, cq * static_cast<uint32_t>(hw) + (lane < CT ? r0 : r1) + xe));
-                    }
+                    // Every lane loads (lanes from 2C up repeat lanes C .. 2C-1):
+                    // without a branch the gather stays one block, which keeps
+                    // its samples' live ranges short.
+                    const uint32_t cq = static_cast<uint32_t>(lane % CT);
+                    const uint32_t xe = static_cast<uint32_t>(min(sx0 + kSegW - ox[0], w - 1));
+                    const float ex =
+                        to_f32(*at(img, cq * static_cast<uint32_t>(hw) + (lane < CT ? r0 : r1) + xe));
 #pragma unroll
                     for (int ch = 0; ch < CT; ++ch) {
                         const uint32_t pl = static_cast<uint32_t>(ch) * static_cast<uint32_t>(hw);
