@@ -3,7 +3,10 @@
 
 One step = the whole hot path over one batch: the fused K-phase forward warp
 (output frames, validity mask, invalid counts) followed by the adjoint
-(image and motion gradients) for the same batch. Default workload: 8 frames
+(image and motion gradients) for the same batch, as a training step runs
+them: the forward also records the adjoint's footprint (the tap box and
+offsets of every row segment) and the adjoint takes it from there. The same
+calls on their own are timed too and reported beside. Default workload: 8 frames
 of 1920x1080 RGBA stored as float32, pan + 16 moving rectangles, 3 phases
 (1/4, 2/4, 3/4). Inputs are resident in device memory before timing starts;
 two complete buffer sets alternate between steps so that one step's data is
@@ -135,7 +138,7 @@ class Workload:
             }
             import paper_2307_12607_amd as exw
             nb = exw.exw_warp_backward_workspace_bytes(tdt, n, c, h, w)
-            s["ws"] = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+            s["ws"] = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
             self.sets.append(s)
         self.b = 4 if dtype == "f32" else 2
         self.fwd_bytes, self.bwd_bytes = algorithmic_bytes(n, c, h, w, k, self.b)
@@ -145,7 +148,10 @@ class Workload:
         n, c, h, w, k = self.shape
         return f"config{self.spec.index}: {n}x{w}x{h} C={c} K={k} {self.dtype}"
 
-    def run(self, steps, warmup):
+    def run(self, steps, warmup, recorded=True):
+        """Time forward + backward steps. recorded: the training pair (the
+        forward records the adjoint's footprint, the adjoint skips that pass);
+        else the standalone calls."""
         import paper_2307_12607_amd as exw
         torch = self.torch
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
@@ -154,12 +160,16 @@ class Workload:
             s = self.sets[i % len(self.sets)]
             if ev:
                 ev[0].record()
-            exw.exw_warp_forward_batched(s["src"], s["mv"], self.phases, s["out"], s["mask"],
-                                         s["count"])
+            if recorded:
+                exw.exw_warp_forward_batched_record(s["src"], s["mv"], self.phases, s["out"],
+                                                    s["ws"], s["mask"], s["count"])
+            else:
+                exw.exw_warp_forward_batched(s["src"], s["mv"], self.phases, s["out"], s["mask"],
+                                             s["count"])
             if ev:
                 ev[1].record()
             exw.exw_warp_backward_batched(s["src"], s["mv"], self.phases, s["gout"], s["gsrc"],
-                                          s["gmv"], s["ws"])
+                                          s["gmv"], s["ws"], recorded=recorded)
             if ev:
                 ev[2].record()
 
@@ -335,6 +345,8 @@ def main():
 
     main_wl = Workload(args.config, args.dtype, dev)
     r = main_wl.run(args.steps, args.warmup)
+    # the same calls without the recorded footprint (an adjoint called on its own)
+    alone = main_wl.run(max(5, args.steps // 3), 2, recorded=False)
     n, c, h, w, k = main_wl.shape
     dominant = "warp_backward" if r["bwd_ms"] >= r["fwd_ms"] else "warp_forward"
     dom_ms = r["bwd_ms"] if dominant == "warp_backward" else r["fwd_ms"]
@@ -396,7 +408,11 @@ def main():
                       "fwd_mpix_s": round(r["fwd_mpix_s"], 1),
                       "fwd_gbs": round(r["fwd_gbs"], 1), "bwd_gbs": round(r["bwd_gbs"], 1),
                       "fwd_alg_bytes": main_wl.fwd_bytes, "bwd_alg_bytes": main_wl.bwd_bytes,
-                      "copy_ceiling_gbs": round(ceiling, 1)},
+                      "copy_ceiling_gbs": round(ceiling, 1),
+                      "step": "forward recording the adjoint's footprint + adjoint from it",
+                      "standalone_calls": {"fwd_ms": round(alone["fwd_ms"], 4),
+                                           "bwd_ms": round(alone["bwd_ms"], 4),
+                                           "fwd_bwd_mpix_s": round(alone["mpix_s"], 1)}},
         "variants": variants,
         "motion_stats": stats_line,
         "frame_quality": quality_line,

@@ -156,6 +156,40 @@ exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_
                              float *grad_mv, void *workspace, size_t workspace_bytes,
                              void *stream);
 
+/*
+ * Training pair: the forward and its adjoint with the adjoint's first pass
+ * (the footprint of every 64-pixel output row segment: the box its taps
+ * cover and, under rigid motion, its integer tap offsets) done inside the
+ * forward, which already forms every displacement and tap offset.
+ *
+ * exw_warp_forward_batched_record: exw_warp_forward_batched, plus the
+ *   footprint of this motion and these phases written into `workspace`
+ *   (device memory of at least exw_warp_backward_workspace_bytes(dtype, n, c,
+ *   h, w) bytes, 256-byte aligned, disjoint from every input and output;
+ *   required unless the batch is empty). The outputs equal those of
+ *   exw_warp_forward_batched.
+ * exw_warp_backward_batched_recorded: exw_warp_backward_batched, taking the
+ *   footprint from `workspace` instead of computing it. The caller guarantees
+ *   that the workspace was last written by exw_warp_forward_batched_record
+ *   with the same mv contents, phases, dtype and shape, on this stream or
+ *   ordered before this call; anything else gives wrong image gradients
+ *   (not detected). Validation and errors are those of
+ *   exw_warp_backward_batched; the workspace is still the adjoint's scratch.
+ */
+exw_status exw_warp_forward_batched_record(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                           int32_t h, int32_t w, const float *mv,
+                                           const float *phases, int32_t k, void *out,
+                                           uint8_t *mask, uint32_t *invalid_count,
+                                           void *workspace, size_t workspace_bytes,
+                                           void *stream);
+
+exw_status exw_warp_backward_batched_recorded(const void *src, exw_dtype dtype, int32_t n,
+                                              int32_t c, int32_t h, int32_t w, const float *mv,
+                                              const float *phases, int32_t k,
+                                              const void *grad_out, void *grad_src,
+                                              float *grad_mv, void *workspace,
+                                              size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Scene-state statistics that accompany a warp.
  *

@@ -29,6 +29,7 @@ from ._capi import ExwError, lib  # noqa: F401  (lib() raises if the library is 
 from .binding import (  # noqa: F401
     exw_warp_backward,
     exw_warp_backward_batched,
+    exw_warp_backward_batched_recorded,
     exw_warp_backward_workspace_bytes,
     exw_decision_plan,
     exw_frame_quality,
@@ -39,6 +40,7 @@ from .binding import (  # noqa: F401
     exw_motion_stats_workspace_bytes,
     exw_warp_forward,
     exw_warp_forward_batched,
+    exw_warp_forward_batched_record,
 )
 
 # Fail at import, not at first use, when the native library is absent.
@@ -68,20 +70,26 @@ def warp(src: torch.Tensor, mv: torch.Tensor, phases: Sequence[float] = (1.0,), 
     return res[0] if len(res) == 1 else tuple(res)
 
 
-def warp_backward(src, mv, phases, grad_out, *, need_src: bool = True, need_mv: bool = True):
-    """Gradients of the batched warp: ``(grad_src or None, grad_mv or None)``."""
+def warp_backward(src, mv, phases, grad_out, *, need_src: bool = True, need_mv: bool = True,
+                  recorded_workspace: torch.Tensor | None = None):
+    """Gradients of the batched warp: ``(grad_src or None, grad_mv or None)``.
+
+    ``recorded_workspace``: the workspace a recording forward
+    (``exw_warp_forward_batched_record``) filled for this motion and these
+    phases; the adjoint then skips its footprint pass.
+    """
     grad_out = grad_out.contiguous()
     n, k, c, h, w = grad_out.shape
     dev = grad_out.device
     gs = torch.empty((n, c, h, w), dtype=grad_out.dtype, device=dev) if need_src else None
     gm = torch.empty((n, 2, h, w), dtype=torch.float32, device=dev) if need_mv else None
-    ws = None
-    if need_src:
+    ws = recorded_workspace
+    if need_src and ws is None:
         nbytes = exw_warp_backward_workspace_bytes(grad_out.dtype, n, c, h, w)
         if nbytes:
             ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     exw_warp_backward_batched(src.contiguous() if need_mv else None, mv.contiguous(), phases,
-                              grad_out, gs, gm, ws)
+                              grad_out, gs, gm, ws, recorded=recorded_workspace is not None)
     return gs, gm
 
 
@@ -95,7 +103,18 @@ class WarpFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, src, mv, phases):
         phases = tuple(float(s) for s in phases)
-        out = warp(src, mv, phases)
+        src, mv = src.contiguous(), mv.contiguous()
+        n, c, h, w = src.shape
+        out = torch.empty((n, len(phases), c, h, w), dtype=src.dtype, device=src.device)
+        ctx.ws = None
+        if ctx.needs_input_grad[0]:
+            # the image gradient will be needed: the forward also records the
+            # adjoint's footprint, and the backward skips that pass
+            nbytes = exw_warp_backward_workspace_bytes(src.dtype, n, c, h, w)
+            ctx.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=src.device)
+            exw_warp_forward_batched_record(src, mv, phases, out, ctx.ws)
+        else:
+            exw_warp_forward_batched(src, mv, phases, out)
         ctx.phases = phases
         ctx.save_for_backward(src, mv)
         return out
@@ -107,7 +126,8 @@ class WarpFunction(torch.autograd.Function):
         if not (need_src or need_mv):
             return None, None, None
         gs, gm = warp_backward(src, mv, ctx.phases, grad_out.to(src.dtype),
-                               need_src=need_src, need_mv=need_mv)
+                               need_src=need_src, need_mv=need_mv,
+                               recorded_workspace=ctx.ws if need_src else None)
         return gs, gm, None
 
 
@@ -206,8 +226,10 @@ def decision_path_frames(src: torch.Tensor, mv: torch.Tensor, path: dict, extrap
 
 __all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differentiable",
            "motion_stats", "frame_quality", "warp_chain", "plan", "threshold_policy",
-           "decision_path_frames", "exw_warp_forward", "exw_warp_forward_batched", "exw_warp_backward",
-           "exw_warp_backward_batched", "exw_warp_backward_workspace_bytes", "exw_motion_stats",
+           "decision_path_frames", "exw_warp_forward", "exw_warp_forward_batched",
+           "exw_warp_forward_batched_record", "exw_warp_backward", "exw_warp_backward_batched",
+           "exw_warp_backward_batched_recorded", "exw_warp_backward_workspace_bytes",
+           "exw_motion_stats",
            "exw_motion_stats_workspace_bytes", "exw_frame_quality",
            "exw_frame_quality_workspace_bytes", "exw_warp_chain", "exw_decision_plan",
            "exw_threshold_policy"]

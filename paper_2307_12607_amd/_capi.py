@@ -35,6 +35,10 @@ SIGNATURES = {
                                                  _i32, _p, _p, _p, _p, _sz, _p]),
     "exw_warp_backward": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _p, _f, _p, _p, _p,
                                          _p, _sz, _p]),
+    "exw_warp_forward_batched_record": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _i32,
+                                                       _p, _p, _i32, _p, _p, _p, _p, _sz, _p]),
+    "exw_warp_backward_batched_recorded": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _i32,
+                                                          _p, _p, _i32, _p, _p, _p, _p, _sz, _p]),
     "exw_motion_stats_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "exw_motion_stats": (ctypes.c_int, [_p, _i32, _i32, _i32, _p, _p, _sz, _p]),
     "exw_frame_quality_workspace_bytes": (_sz, [_i32, _i32, _i32, _i32]),

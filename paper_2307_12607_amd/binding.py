@@ -83,6 +83,30 @@ def exw_warp_forward_batched(src: torch.Tensor, mv: torch.Tensor, phases, out: t
     check(st, "exw_warp_forward_batched")
 
 
+def exw_warp_forward_batched_record(src: torch.Tensor, mv: torch.Tensor, phases, out: torch.Tensor,
+                                    workspace: torch.Tensor, mask: Optional[torch.Tensor] = None,
+                                    invalid_count: Optional[torch.Tensor] = None,
+                                    stream=None) -> None:
+    """exw_warp_forward_batched, also leaving the adjoint's footprint of this
+    motion and these phases in ``workspace`` (a byte tensor of at least
+    ``exw_warp_backward_workspace_bytes`` bytes) for
+    exw_warp_backward_batched_recorded."""
+    dev = src.device
+    _dev(src, "src", dev)
+    n, c, h, w = src.shape
+    arr, k = _phases(phases)
+    _expect(mv, "mv", (n, 2, h, w), torch.float32, dev)
+    _expect(out, "out", (n, k, c, h, w), src.dtype, dev)
+    _expect(mask, "mask", (n, k, h, w), torch.uint8, dev)
+    _expect(invalid_count, "invalid_count", (n, k), torch.int32, dev)
+    _dev(workspace, "workspace", dev)
+    st = lib().exw_warp_forward_batched_record(
+        _ptr(src), exw_dtype(src.dtype), n, c, h, w, _ptr(mv), arr, k, _ptr(out), _ptr(mask),
+        _ptr(invalid_count), _ptr(workspace), workspace.numel() * workspace.element_size(),
+        _stream(dev, stream))
+    check(st, "exw_warp_forward_batched_record")
+
+
 def exw_warp_forward(src: torch.Tensor, mv: torch.Tensor, phase: float, out: torch.Tensor,
                      mask: Optional[torch.Tensor] = None, stream=None) -> None:
     """One frame: src [C,H,W], mv [2,H,W] f32, out [C,H,W], mask [H,W] u8."""
@@ -105,7 +129,8 @@ def exw_warp_backward_workspace_bytes(dtype: torch.dtype, n: int, c: int, h: int
 def exw_warp_backward_batched(src: Optional[torch.Tensor], mv: torch.Tensor, phases,
                               grad_out: torch.Tensor, grad_src: Optional[torch.Tensor] = None,
                               grad_mv: Optional[torch.Tensor] = None,
-                              workspace: Optional[torch.Tensor] = None, stream=None) -> None:
+                              workspace: Optional[torch.Tensor] = None, stream=None,
+                              recorded: bool = False) -> None:
     """grad_out [N,K,C,H,W] -> grad_src [N,C,H,W] (dtype of grad_out) and/or
     grad_mv [N,2,H,W] f32. ``workspace``: a byte tensor of at least
     ``exw_warp_backward_workspace_bytes`` bytes (needed for f16/bf16 grad_src)."""
@@ -124,10 +149,24 @@ def exw_warp_backward_batched(src: Optional[torch.Tensor], mv: torch.Tensor, pha
     if workspace is not None:
         _dev(workspace, "workspace", dev)
         ws_bytes = workspace.numel() * workspace.element_size()
-    st = lib().exw_warp_backward_batched(_ptr(src), exw_dtype(dt), n, c, h, w, _ptr(mv), arr, k,
-                                         _ptr(grad_out), _ptr(grad_src), _ptr(grad_mv),
-                                         _ptr(workspace), ws_bytes, _stream(dev, stream))
-    check(st, "exw_warp_backward_batched")
+    name = "exw_warp_backward_batched_recorded" if recorded else "exw_warp_backward_batched"
+    st = getattr(lib(), name)(_ptr(src), exw_dtype(dt), n, c, h, w, _ptr(mv), arr, k,
+                              _ptr(grad_out), _ptr(grad_src), _ptr(grad_mv),
+                              _ptr(workspace), ws_bytes, _stream(dev, stream))
+    check(st, name)
+
+
+def exw_warp_backward_batched_recorded(src: Optional[torch.Tensor], mv: torch.Tensor, phases,
+                                       grad_out: torch.Tensor,
+                                       grad_src: Optional[torch.Tensor] = None,
+                                       grad_mv: Optional[torch.Tensor] = None,
+                                       workspace: Optional[torch.Tensor] = None,
+                                       stream=None) -> None:
+    """exw_warp_backward_batched with the footprint that
+    exw_warp_forward_batched_record left in ``workspace`` for the same motion,
+    phases, dtype and shape."""
+    exw_warp_backward_batched(src, mv, phases, grad_out, grad_src, grad_mv, workspace, stream,
+                              recorded=True)
 
 
 def exw_warp_backward(src: Optional[torch.Tensor], mv: torch.Tensor, phase: float,
@@ -245,8 +284,9 @@ def exw_threshold_policy(motion_stats, invalid_fraction, max_variance: float,
     return tuple(dec)
 
 
-__all__ = ["ExwError", "exw_dtype", "exw_warp_forward_batched", "exw_warp_forward",
-           "exw_warp_backward_workspace_bytes", "exw_warp_backward_batched", "exw_warp_backward",
+__all__ = ["ExwError", "exw_dtype", "exw_warp_forward_batched", "exw_warp_forward_batched_record",
+           "exw_warp_forward", "exw_warp_backward_workspace_bytes", "exw_warp_backward_batched",
+           "exw_warp_backward_batched_recorded", "exw_warp_backward",
            "exw_motion_stats_workspace_bytes", "exw_motion_stats",
            "exw_frame_quality_workspace_bytes", "exw_frame_quality", "exw_warp_chain",
            "exw_decision_plan", "exw_threshold_policy", "_capi"]

@@ -173,28 +173,12 @@ WsLayout workspace_layout(int dtype, int n, int c, int h, int w) {
         if (st_ != EXW_SUCCESS) return st_;            \
     } while (0)
 
-}  // namespace
-
-extern "C" {
-
-int exw_abi_version(void) { return EXW_ABI_VERSION; }
-
-const char *exw_status_string(int status) {
-    switch (status) {
-    case EXW_SUCCESS: return "EXW_SUCCESS";
-    case EXW_ERROR_INVALID_VALUE: return "EXW_ERROR_INVALID_VALUE";
-    case EXW_ERROR_UNSUPPORTED: return "EXW_ERROR_UNSUPPORTED";
-    case EXW_ERROR_LAUNCH: return "EXW_ERROR_LAUNCH";
-    default: return "EXW_UNKNOWN_STATUS";
-    }
-}
-
-const char *exw_last_error(void) { return g_last_error.c_str(); }
-
-exw_status exw_warp_forward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
-                                    int32_t h, int32_t w, const float *mv, const float *phases,
-                                    int32_t k, void *out, uint8_t *mask,
-                                    uint32_t *invalid_count, void *stream) {
+// The forward; with `record`, it also leaves the adjoint's footprint of this
+// motion and these phases in the caller's adjoint workspace.
+exw_status forward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                        int32_t w, const float *mv, const float *phases, int32_t k, void *out,
+                        uint8_t *mask, uint32_t *invalid_count, void *workspace,
+                        size_t workspace_bytes, bool record, void *stream) {
     Checked ck;
     EXW_TRY(check_common(dtype, n, c, h, w, phases, k, &ck));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -209,34 +193,37 @@ exw_status exw_warp_forward_batched(const void *src, exw_dtype dtype, int32_t n,
     EXW_TRY(check_ptr("mv", mv, 4, true));
     EXW_TRY(check_ptr("out", out, ck.esize, true));
     EXW_TRY(check_ptr("mask", mask, 1, false));
+    const WsLayout lay = workspace_layout(dtype, n, c, h, w);
+    const uint64_t ws_need = record ? lay.total : 0;
+    if (record) {
+        EXW_TRY(check_ptr("workspace", workspace, 256, true));
+        if (workspace_bytes < ws_need)
+            return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %llu",
+                        workspace_bytes, (unsigned long long)ws_need);
+    }
     const Span ins[] = {span("src", src, ck.img_elems * ck.esize),
                         span("mv", mv, ck.mv_elems * 4)};
     const Span outs[] = {span("out", out, ck.out_elems * ck.esize),
                          span("mask", mask, nk * ck.hw),
-                         span("invalid_count", invalid_count, nk * 4)};
-    EXW_TRY(check_disjoint(outs, 3, ins, 2));
-    return launched(exw::launch_forward(dtype, src, mv, ck.shape, out, mask, invalid_count, st),
+                         span("invalid_count", invalid_count, nk * 4),
+                         span("workspace", record ? workspace : nullptr, ws_need)};
+    EXW_TRY(check_disjoint(outs, 4, ins, 2));
+    if (!record)
+        return launched(exw::launch_forward(dtype, src, mv, ck.shape, out, mask, invalid_count, st),
+                        "warp forward launch");
+    char *base = static_cast<char *>(workspace);
+    const exw::BwdWorkspace ws{base + lay.boxes, base + lay.info, nullptr, false};
+    return launched(exw::launch_forward_record(dtype, src, mv, ck.shape, out, mask, invalid_count,
+                                               ws, st),
                     "warp forward launch");
 }
 
-exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,
-                            const float *mv, float phase, void *out, uint8_t *mask,
-                            void *stream) {
-    return exw_warp_forward_batched(src, dtype, 1, c, h, w, mv, &phase, 1, out, mask, nullptr,
-                                    stream);
-}
-
-size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
-                                         int32_t w) {
-    if (dtype_size(dtype) == 0 || n <= 0 || c <= 0 || h <= 0 || w <= 0) return 0;
-    return workspace_layout(dtype, n, c, h, w).total;
-}
-
-exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
-                                     int32_t h, int32_t w, const float *mv, const float *phases,
-                                     int32_t k, const void *grad_out, void *grad_src,
-                                     float *grad_mv, void *workspace, size_t workspace_bytes,
-                                     void *stream) {
+// The adjoint; with `recorded`, the footprint in the workspace is taken as
+// left there by the recording forward of the same motion and phases.
+exw_status backward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                         int32_t w, const float *mv, const float *phases, int32_t k,
+                         const void *grad_out, void *grad_src, float *grad_mv, void *workspace,
+                         size_t workspace_bytes, bool recorded, void *stream) {
     Checked ck;
     EXW_TRY(check_common(dtype, n, c, h, w, phases, k, &ck));
     if (ck.empty || (!grad_src && !grad_mv)) return succeed();
@@ -261,7 +248,7 @@ exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n
                          span("grad_mv", grad_mv, ck.mv_elems * 4),
                          span("workspace", needs_ws ? workspace : nullptr, ws_need)};
     EXW_TRY(check_disjoint(outs, 3, ins, 3));
-    exw::BwdWorkspace ws{nullptr, nullptr, nullptr};
+    exw::BwdWorkspace ws{nullptr, nullptr, nullptr, recorded};
     if (needs_ws) {
         char *base = static_cast<char *>(workspace);
         ws.boxes = base + lay.boxes;
@@ -272,6 +259,74 @@ exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n
                                          grad_src, grad_mv, ws,
                                          static_cast<hipStream_t>(stream)),
                     "warp backward launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int exw_abi_version(void) { return EXW_ABI_VERSION; }
+
+const char *exw_status_string(int status) {
+    switch (status) {
+    case EXW_SUCCESS: return "EXW_SUCCESS";
+    case EXW_ERROR_INVALID_VALUE: return "EXW_ERROR_INVALID_VALUE";
+    case EXW_ERROR_UNSUPPORTED: return "EXW_ERROR_UNSUPPORTED";
+    case EXW_ERROR_LAUNCH: return "EXW_ERROR_LAUNCH";
+    default: return "EXW_UNKNOWN_STATUS";
+    }
+}
+
+const char *exw_last_error(void) { return g_last_error.c_str(); }
+
+exw_status exw_warp_forward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                    int32_t h, int32_t w, const float *mv, const float *phases,
+                                    int32_t k, void *out, uint8_t *mask,
+                                    uint32_t *invalid_count, void *stream) {
+    return forward_impl(src, dtype, n, c, h, w, mv, phases, k, out, mask, invalid_count, nullptr,
+                        0, false, stream);
+}
+
+exw_status exw_warp_forward_batched_record(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                           int32_t h, int32_t w, const float *mv,
+                                           const float *phases, int32_t k, void *out,
+                                           uint8_t *mask, uint32_t *invalid_count,
+                                           void *workspace, size_t workspace_bytes,
+                                           void *stream) {
+    return forward_impl(src, dtype, n, c, h, w, mv, phases, k, out, mask, invalid_count,
+                        workspace, workspace_bytes, true, stream);
+}
+
+exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,
+                            const float *mv, float phase, void *out, uint8_t *mask,
+                            void *stream) {
+    return exw_warp_forward_batched(src, dtype, 1, c, h, w, mv, &phase, 1, out, mask, nullptr,
+                                    stream);
+}
+
+size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
+                                         int32_t w) {
+    if (dtype_size(dtype) == 0 || n <= 0 || c <= 0 || h <= 0 || w <= 0) return 0;
+    return workspace_layout(dtype, n, c, h, w).total;
+}
+
+exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
+                                     int32_t h, int32_t w, const float *mv, const float *phases,
+                                     int32_t k, const void *grad_out, void *grad_src,
+                                     float *grad_mv, void *workspace, size_t workspace_bytes,
+                                     void *stream) {
+    return backward_impl(src, dtype, n, c, h, w, mv, phases, k, grad_out, grad_src, grad_mv,
+                         workspace, workspace_bytes, false, stream);
+}
+
+exw_status exw_warp_backward_batched_recorded(const void *src, exw_dtype dtype, int32_t n,
+                                              int32_t c, int32_t h, int32_t w, const float *mv,
+                                              const float *phases, int32_t k,
+                                              const void *grad_out, void *grad_src,
+                                              float *grad_mv, void *workspace,
+                                              size_t workspace_bytes, void *stream) {
+    return backward_impl(src, dtype, n, c, h, w, mv, phases, k, grad_out, grad_src, grad_mv,
+                         workspace, workspace_bytes, true, stream);
 }
 
 exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,

@@ -28,15 +28,33 @@ struct BwdWorkspace {
     void *boxes;     // per row segment: bounding box of its taps
     void *info;      // per frame: reach of the segments, far flag
     float *accum32;  // float32 image-gradient accumulator (16-bit storage only)
+    bool recorded;   // boxes and info already hold the footprint of this motion and these phases
 };
 
 size_t backward_box_bytes(int n, int h, int w);
 size_t backward_info_bytes(int n);
 
+// Whether the adjoint of C channels reads the footprint records (its tile path).
+bool backward_uses_footprint(int c);
+
+// The adjoint's footprint pass alone (records into ws.boxes, ws.info).
+hipError_t launch_footprint(const float *mv, const WarpShape &s, const BwdWorkspace &ws,
+                            hipStream_t stream);
+
+// The per-frame figures of ws.info (reach of the near segments, far flag)
+// from the boxes already in ws.boxes; ws.info must hold zeros.
+hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, hipStream_t stream);
+
 hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t stream);
 
 hipError_t launch_forward(int dtype, const void *src, const float *mv, const WarpShape &s,
                           void *out, uint8_t *mask, uint32_t *count, hipStream_t stream);
+
+// The forward, also recording the adjoint's footprint into ws (when the
+// adjoint of this channel count reads it).
+hipError_t launch_forward_record(int dtype, const void *src, const float *mv, const WarpShape &s,
+                                 void *out, uint8_t *mask, uint32_t *count,
+                                 const BwdWorkspace &ws, hipStream_t stream);
 
 // grad_src / grad_mv may each be NULL (not requested). The workspace is used
 // only when grad_src is requested.

@@ -23,8 +23,7 @@
 //     to a fallback that scatters with global atomics (frames without such
 //     segments cost one check). For 16-bit storage such frames accumulate in a
 //     float32 workspace and pass 4 rounds it into the output.
-#include <climits>
-
+#include "footprint.h"
 #include "launch.h"
 #include "warp_common.h"
 
@@ -33,26 +32,7 @@ namespace {
 
 constexpr int kTileW = 128;      // width of an image-gradient tile (pass 2)
 constexpr int kThreads = 256;    // four wavefronts
-constexpr int kFar = 128;        // segments reaching further use the atomic fallback
 constexpr int kFarBlocks = 1024; // grid of the fallback and cast passes
-
-struct Box {
-    int x_lo, x_hi, y_lo, y_hi;  // inclusive; x_lo > x_hi when the segment has no valid tap
-};
-
-// Integer tap offsets of a "uniform" segment: every lane is valid in every
-// phase and all 64 lanes share ceil(s_k * u) and ceil(s_k * v), packed per
-// phase k as (cx & 0xffff) | (cy << 16). Other segments hold kNotUniform in
-// word 0 (offsets of uniform segments lie in [-32767, 32767]).
-struct SegOffsets {
-    uint32_t k[4];
-};
-constexpr uint32_t kNotUniform = 0x80008000u;
-
-struct FrameInfo {
-    int reach;    // largest distance (px) between a near segment and its box
-    int has_far;  // 1 if a segment of this frame reaches further than kFar
-};
 
 template <typename T>
 struct BwdArgs {
@@ -71,12 +51,6 @@ struct BwdArgs {
     int frame_32bit;  // C * H * W * sizeof(T) < 2^32: frame-relative 32-bit offsets
     float s[4];
 };
-
-__device__ __forceinline__ int box_reach(const Box &b, int sx0, int row) {
-    const int r = max(max(sx0 - b.x_lo, b.x_hi - (sx0 + kSegW - 1)),
-                      max(row - b.y_lo, b.y_hi - row));
-    return max(r, 0);
-}
 
 // ---------------------------------------------------------------- pass 1
 
@@ -129,61 +103,14 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
 #pragma unroll
     for (int r = 0; r < kFootRows; ++r) {
         const int y = y0 + r;
-        const bool in_r = x < w && y < h;
-        bool uniform = true;  // wave-uniform
-        uint32_t packed[KT];
-        bool okj[KT];
-        int cxj[KT], cyj[KT];
-        int cx_lo = INT_MAX, cx_hi = INT_MIN, cy_lo = INT_MAX, cy_hi = INT_MIN;
-#pragma unroll
-        for (int j = 0; j < KT; ++j) {
-            const float dx = ph.s[j] * u[r], dy = ph.s[j] * v[r];
-            // the validity test of the warp: x - (w-1) <= dx <= x, likewise for y
-            okj[j] = in_r && dx <= static_cast<float>(x) && dx >= static_cast<float>(x - (w - 1)) &&
-                     dy <= static_cast<float>(y) && dy >= static_cast<float>(y - (h - 1));
-            cxj[j] = static_cast<int>(ceilf(okj[j] ? dx : 0.0f));
-            cyj[j] = static_cast<int>(ceilf(okj[j] ? dy : 0.0f));
-            const int rcx = __builtin_amdgcn_readfirstlane(cxj[j]);
-            const int rcy = __builtin_amdgcn_readfirstlane(cyj[j]);
-            uniform = uniform && __ballot(okj[j] && cxj[j] == rcx && cyj[j] == rcy) == ~0ull &&
-                      static_cast<unsigned>(rcx + 32767) <= 65534u &&
-                      static_cast<unsigned>(rcy + 32767) <= 65534u;
-            packed[j] = (static_cast<uint32_t>(rcx) & 0xffffu) | (static_cast<uint32_t>(rcy) << 16);
-            cx_lo = min(cx_lo, rcx); cx_hi = max(cx_hi, rcx);
-            cy_lo = min(cy_lo, rcy); cy_hi = max(cy_hi, rcy);
-        }
-        // first taps x0 = x - ceil(dx) (the exact floor of x - dx), y0 likewise
         int b[4];
-        if (uniform) {
-            b[0] = sx0 - cx_hi; b[1] = sx0 + kSegW - 1 - cx_lo;
-            b[2] = y - cy_hi;   b[3] = y - cy_lo;
-        } else {  // branch-free per lane: invalid phases leave the box as is
-            int xl = INT_MAX, xh = INT_MIN, yl = INT_MAX, yh = INT_MIN;
-#pragma unroll
-            for (int j = 0; j < KT; ++j) {
-                xl = min(xl, okj[j] ? x - cxj[j] : INT_MAX);
-                xh = max(xh, okj[j] ? x - cxj[j] : INT_MIN);
-                yl = min(yl, okj[j] ? y - cyj[j] : INT_MAX);
-                yh = max(yh, okj[j] ? y - cyj[j] : INT_MIN);
-            }
-            b[0] = __builtin_amdgcn_readfirstlane(wave_min(xl));
-            b[1] = __builtin_amdgcn_readfirstlane(wave_max(xh));
-            b[2] = __builtin_amdgcn_readfirstlane(wave_min(yl));
-            b[3] = __builtin_amdgcn_readfirstlane(wave_max(yh));
-        }
-        if (b[0] > b[1] || y >= h) {
-            b[0] = 1; b[1] = 0; b[2] = 1; b[3] = 0;  // no valid tap
-        } else {
-            // the second tap is x0 + 1 clamped to the frame, applied to the maximum
-            b[1] = min(b[1] + 1, w - 1);
-            b[3] = min(b[3] + 1, h - 1);
-            const int rr = box_reach(Box{b[0], b[1], b[2], b[3]}, sx0, y);
-            if (rr > kFar) far = 1; else reach_max = max(reach_max, rr);
-        }
+        uint32_t rr[KT];
+        segment_footprint<KT>(u[r], v[r], x, y, sx0, w, h, x < w && y < h, ph.s, b, rr);
+        note_reach(b, sx0, y, reach_max, far);
         if (lane == r) {
             mine = Box{b[0], b[1], b[2], b[3]};
 #pragma unroll
-            for (int j = 0; j < KT; ++j) rec[j] = uniform ? packed[j] : (j == 0 ? kNotUniform : 0u);
+            for (int j = 0; j < KT; ++j) rec[j] = rr[j];
         }
     }
     if (lane < kFootRows && y0 + lane < h) {
@@ -194,11 +121,49 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
         for (int j = 0; j < KT; ++j) o.k[j] = rec[j];
         offs[at_seg] = o;
     }
-    if (lane == 0) {
-        if (far) atomicMax(&info[in].has_far, 1);
-        if (reach_max > __hip_atomic_load(&info[in].reach, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&info[in].reach, reach_max);  // rare: the value only grows
+    if (lane == 0) publish_reach(&info[in], reach_max, far);
+}
+
+// Per-frame figures from recorded boxes: what the footprint pass accumulates
+// as it goes, for boxes the forward recorded. Blocks (y: frame) take
+// kReachPerThread segments per thread, all loads in flight at once, reduce
+// through LDS and update the frame once per block (updates of one address
+// serialise: few of them, and no wavefront waits on more than one).
+constexpr int kReachPerThread = 4;
+
+__global__ __launch_bounds__(kThreads) void frame_reach_kernel(const Box *boxes, FrameInfo *info,
+                                                               int h, int segs) {
+    __shared__ int red[2][kThreads / kSegW];
+    const int in = blockIdx.y;
+    const int per_frame = h * segs;  // below 2^31: the C ABI bounds H * W
+    const Box *fb = boxes + static_cast<int64_t>(in) * per_frame;
+    const int i0 = blockIdx.x * (kThreads * kReachPerThread) + threadIdx.x;
+    Box bx[kReachPerThread];
+#pragma unroll
+    for (int j = 0; j < kReachPerThread; ++j) {
+        const int i = i0 + j * kThreads;
+        bx[j] = i < per_frame ? fb[i] : Box{1, 0, 1, 0};
+    }
+    int reach_max = -1, far = 0;
+#pragma unroll
+    for (int j = 0; j < kReachPerThread; ++j) {
+        const int i = i0 + j * kThreads;
+        const int row = i / segs;
+        const int b[4] = {bx[j].x_lo, bx[j].x_hi, bx[j].y_lo, bx[j].y_hi};
+        note_reach(b, (i - row * segs) * kSegW, row, reach_max, far);
+    }
+    reach_max = wave_max(reach_max);
+    far = wave_max(far);
+    const int wave = threadIdx.x / kSegW;
+    if (threadIdx.x % kSegW == 0) { red[0][wave] = reach_max; red[1][wave] = far; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 1; q < kThreads / kSegW; ++q) {
+            reach_max = max(reach_max, red[0][q]);
+            far = max(far, red[1][q]);
+        }
+        publish_reach(info + in, reach_max, far);
     }
 }
 
@@ -919,6 +884,23 @@ hipError_t run_generic(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
 
 // ---------------------------------------------------------------- launchers
 
+// Pass 1 over N frames: zero the per-frame figures, then the footprint kernel.
+template <int KT>
+hipError_t footprint_pass(const float *mv, Box *boxes, SegOffsets *offs, FrameInfo *info, int n,
+                          int h, int w, const float *s, hipStream_t st) {
+    hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(info), static_cast<int64_t>(n) * 2, st);
+    if (e != hipSuccess) return e;
+    Phases4 ph;
+    for (int j = 0; j < 4; ++j) ph.s[j] = s[j];
+    const int segs = (w + kSegW - 1) / kSegW;
+    const int64_t foot_units = static_cast<int64_t>(n) * ((h + kFootRows - 1) / kFootRows) * segs;
+    const unsigned foot_blocks =
+        static_cast<unsigned>((foot_units + kThreads / kSegW - 1) / (kThreads / kSegW));
+    hipLaunchKernelGGL((footprint_kernel<KT>), dim3(foot_blocks), dim3(kThreads), 0, st, mv,
+                       boxes, offs, info, n, h, w, segs, ph);
+    return hipGetLastError();
+}
+
 int tile_rows_for(int c) {
     // One wavefront per 128 x TH tile of float32 accumulators (2 KB per
     // four-channel row). Taller tiles replay fewer segments (3.5 replays per
@@ -939,18 +921,10 @@ hipError_t run(BwdArgs<T> a, const BwdWorkspace &ws, hipStream_t st) {
                            st, a);
         return hipGetLastError();
     }
-    hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t *>(a.info),
-                                   static_cast<int64_t>(a.n) * 2, st);
-    if (e != hipSuccess) return e;
-    Phases4 ph;
-    for (int j = 0; j < 4; ++j) ph.s[j] = a.s[j];
-    const int64_t foot_units =
-        static_cast<int64_t>(a.n) * ((a.h + kFootRows - 1) / kFootRows) * a.segs;
-    const unsigned foot_blocks =
-        static_cast<unsigned>((foot_units + kThreads / kSegW - 1) / (kThreads / kSegW));
-    hipLaunchKernelGGL((footprint_kernel<KT>), dim3(foot_blocks), dim3(kThreads), 0, st, a.mv,
-                       a.boxes, a.offs, a.info, a.n, a.h, a.w, a.segs, ph);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (!ws.recorded &&  // else the forward left the footprint in the workspace
+        (e = footprint_pass<KT>(a.mv, a.boxes, a.offs, a.info, a.n, a.h, a.w, a.s, st)) != hipSuccess)
+        return e;
 
     const size_t lds = sizeof(float) * CellWidth<CT>::value * a.tile_h * kTileW;
     const int64_t tiles = static_cast<int64_t>(a.n) * a.tiles_x * a.tiles_y;
@@ -1020,6 +994,33 @@ size_t backward_box_bytes(int n, int h, int w) {
 }
 
 size_t backward_info_bytes(int n) { return sizeof(FrameInfo) * static_cast<size_t>(n); }
+
+bool backward_uses_footprint(int c) { return c == 1 || c == 2 || c == 3 || c == 4 || c == 12; }
+
+hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, hipStream_t stream) {
+    const int segs = (s.w + kSegW - 1) / kSegW;
+    const int64_t per_frame = static_cast<int64_t>(s.h) * segs;
+    const unsigned bx = static_cast<unsigned>((per_frame + kThreads * kReachPerThread - 1) /
+                                              (kThreads * kReachPerThread));
+    hipLaunchKernelGGL(frame_reach_kernel, dim3(bx, static_cast<unsigned>(s.n)), dim3(kThreads), 0,
+                       stream, reinterpret_cast<const Box *>(ws.boxes),
+                       reinterpret_cast<FrameInfo *>(ws.info), s.h, segs);
+    return hipGetLastError();
+}
+
+hipError_t launch_footprint(const float *mv, const WarpShape &s, const BwdWorkspace &ws,
+                            hipStream_t stream) {
+    Box *boxes = reinterpret_cast<Box *>(ws.boxes);
+    SegOffsets *offs = reinterpret_cast<SegOffsets *>(
+        boxes + static_cast<size_t>(s.n) * s.h * ((s.w + kSegW - 1) / kSegW));
+    FrameInfo *info = reinterpret_cast<FrameInfo *>(ws.info);
+    switch (s.k) {
+    case 1: return footprint_pass<1>(mv, boxes, offs, info, s.n, s.h, s.w, s.phases, stream);
+    case 2: return footprint_pass<2>(mv, boxes, offs, info, s.n, s.h, s.w, s.phases, stream);
+    case 3: return footprint_pass<3>(mv, boxes, offs, info, s.n, s.h, s.w, s.phases, stream);
+    default: return footprint_pass<4>(mv, boxes, offs, info, s.n, s.h, s.w, s.phases, stream);
+    }
+}
 
 hipError_t launch_backward(int dtype, const void *src, const float *mv, const WarpShape &s,
                            const void *grad_out, void *grad_src, float *grad_mv,

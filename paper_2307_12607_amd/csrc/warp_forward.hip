@@ -21,6 +21,7 @@
 // tiles), so the taps are gathered from global memory; an LDS-staged variant
 // and four pixels per lane were both measured slower. No MFMA: this is a
 // gather.
+#include "footprint.h"
 #include "launch.h"
 #include "warp_common.h"
 
@@ -43,6 +44,15 @@ struct FwdArgs {
     int tiles_x, tiles_y;
     int frame_32bit;  // C * H * W * sizeof(T) < 2^32: frame-relative 32-bit offsets
     float s[4];
+    // The adjoint's footprint records, written when the caller asks for them
+    // (the kernel's REC instantiation): [N][H][segs] boxes and offsets of
+    // the 64-pixel row segments. The per-frame figures are reduced from the
+    // boxes by a pass of their own (one update per wavefront here would hold
+    // every wavefront for a memory round trip); this kernel zeroes them.
+    Box *boxes;
+    SegOffsets *offs;
+    uint32_t *info_words;  // the per-frame figures (2 words per frame), zeroed by block 0
+    int segs;
 };
 
 struct PixelPos {
@@ -356,9 +366,11 @@ __device__ __forceinline__ void store_pair(T *p, float a, float b) {
 // stored at once - half the memory instructions per pixel of the one-pixel
 // path. Phases with the offsets of the previous phase reuse its samples. The
 // blend is that of the one-pixel path, term for term. Returns false, having
-// written nothing, when the segment is not uniform.
+// written nothing, when the segment is not uniform; else true, with the
+// offsets (ceil(s_k u), ceil(s_k v)) of every phase in (orx, ory).
 template <typename T, int CT, int KT>
-__device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &g) {
+__device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &g, int (&orx)[KT],
+                                             int (&ory)[KT]) {
     const int w = a.w, h = a.h, y = g.y;
     const int64_t hw = static_cast<int64_t>(h) * w;
     const uint32_t hw32 = static_cast<uint32_t>(hw);  // the frame spans less than 4 GB
@@ -432,22 +444,82 @@ __device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &
         if (a.mask)  // every pixel valid
             *reinterpret_cast<u16_st *>(a.mask + (static_cast<int64_t>(g.in) * KT + j) * hw + p) = 0x0101;
     }
+#pragma unroll
+    for (int j = 0; j < KT; ++j) { orx[j] = rx[j]; ory[j] = ry[j]; }
     return true;  // no invalid pixel: the zeroed counts stay as they are
+}
+
+// Footprint records of the wavefront's two 64-pixel segments after the
+// two-pixel path: every pixel valid with the offsets (rx, ry) in every phase,
+// so the boxes follow from the offsets (what segment_footprint gives).
+template <typename T, int KT>
+__device__ __forceinline__ void record_pair(const FwdArgs<T> &a, const SegPos &g,
+                                            const int (&rx)[KT], const int (&ry)[KT]) {
+    int b0[4], b1[4];
+    uint32_t rec[KT];
+    uniform_footprint<KT>(rx, ry, g.y, g.sx0, a.w, a.h, b0, rec);
+    uniform_footprint<KT>(rx, ry, g.y, g.sx0 + kSegW, a.w, a.h, b1, rec);
+    const int lane = threadIdx.x;
+    if (lane < 2) {  // lane i stores segment i of the pair
+        const int64_t at = (static_cast<int64_t>(g.in) * a.h + g.y) * a.segs + g.sx0 / kSegW + lane;
+        a.boxes[at] = lane ? Box{b1[0], b1[1], b1[2], b1[3]} : Box{b0[0], b0[1], b0[2], b0[3]};
+        SegOffsets o{{0u, 0u, 0u, 0u}};
+#pragma unroll
+        for (int j = 0; j < KT; ++j) o.k[j] = rec[j];
+        a.offs[at] = o;
+    }
+}
+
+// Footprint records of the wavefront's segments (those inside the frame)
+// after the one-pixel paths: the footprint pass's computation, row by row.
+template <typename T, int KT>
+__device__ __forceinline__ void record_rows(const FwdArgs<T> &a, const SegPos &g) {
+    if (g.y >= a.h) return;  // wave-uniform
+    const int64_t hw = static_cast<int64_t>(a.h) * a.w;
+    const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        const int sx0 = g.sx0 + half * kSegW;
+        if (sx0 >= a.w) break;  // wave-uniform
+        const int x = sx0 + static_cast<int>(threadIdx.x);
+        const bool in_r = x < a.w;
+        const int64_t p = static_cast<int64_t>(g.y) * a.w + x;
+        const float u = in_r ? mu[p] : 0.0f, v = in_r ? mu[hw + p] : 0.0f;
+        int b[4];
+        uint32_t rec[KT];
+        segment_footprint<KT>(u, v, x, g.y, sx0, a.w, a.h, in_r, a.s, b, rec);
+        if (threadIdx.x == 0) {
+            const int64_t at = (static_cast<int64_t>(g.in) * a.h + g.y) * a.segs + sx0 / kSegW;
+            a.boxes[at] = Box{b[0], b[1], b[2], b[3]};
+            SegOffsets o{{0u, 0u, 0u, 0u}};
+#pragma unroll
+            for (int j = 0; j < KT; ++j) o.k[j] = rec[j];
+            a.offs[at] = o;
+        }
+    }
 }
 
 // One 128-pixel row segment per wavefront: two pixels per lane when the whole
 // segment is uniform in every phase, otherwise the one-pixel paths on each
-// half.
-template <typename T, int CT, int KT>
+// half. REC: also write the adjoint's footprint records of the two segments.
+template <typename T, int CT, int KT, bool REC>
 __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
+    if constexpr (REC) {  // ready for the reduction pass that follows (no launch of its own)
+        if (blockIdx.x == 0 && threadIdx.y == 0)
+            for (int i = threadIdx.x; i < 2 * a.n; i += kTileW) a.info_words[i] = 0u;
+    }
     const SegPos g = decode_segment(a.tiles_x, a.tiles_y);
     if constexpr (2 * CT * KT <= kTileW) {
+        int rx[KT], ry[KT];
         if (a.frame_32bit && g.y < a.h && g.sx0 + kSegPair <= a.w &&  // wave-uniform
-            pair_uniform<T, CT, KT>(a, g))
+            pair_uniform<T, CT, KT>(a, g, rx, ry)) {
+            if constexpr (REC) record_pair<T, KT>(a, g, rx, ry);
             return;
+        }
     }
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) forward_row<T, CT, KT>(a, half_pixel(g, half, a.w, a.h));
+    if constexpr (REC) record_rows<T, KT>(a, g);
 }
 
 // Any channel count, any phase count, any width (including W == 1): one
@@ -521,26 +593,45 @@ FwdArgs<T> make_args(const void *src, const float *mv, const WarpShape &s, void 
     a.tiles_y = (s.h + kTileH - 1) / kTileH;
     a.frame_32bit = static_cast<uint64_t>(s.c) * s.h * s.w * sizeof(T) < (uint64_t(1) << 32);
     for (int j = 0; j < 4; ++j) a.s[j] = s.phases[j];
+    a.boxes = nullptr;
+    a.offs = nullptr;
+    a.info_words = nullptr;
+    a.segs = (s.w + kSegW - 1) / kSegW;
     return a;
 }
 
-template <typename T, int CT>
-hipError_t launch_ck(const FwdArgs<T> &a, dim3 grid, hipStream_t st) {
+template <typename T, int CT, bool REC>
+hipError_t launch_ckr(const FwdArgs<T> &a, dim3 grid, hipStream_t st) {
+    const dim3 block(kTileW, kTileH);
     switch (a.k) {
-    case 1: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 1>), grid, dim3(kTileW, kTileH), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 2>), grid, dim3(kTileW, kTileH), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 3>), grid, dim3(kTileW, kTileH), 0, st, a); break;
-    default: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 4>), grid, dim3(kTileW, kTileH), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 1, REC>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 2, REC>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 3, REC>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 4, REC>), grid, block, 0, st, a); break;
     }
     return hipGetLastError();
 }
 
+template <typename T, int CT>
+hipError_t launch_ck(const FwdArgs<T> &a, dim3 grid, hipStream_t st) {
+    return a.boxes ? launch_ckr<T, CT, true>(a, grid, st) : launch_ckr<T, CT, false>(a, grid, st);
+}
+
+// Whether the specialised kernel (which can record the footprint) serves C.
+bool specialised(int c, int w) { return w >= 2 && (c == 1 || c == 3 || c == 4 || c == 12); }
+
 template <typename T>
 hipError_t launch_typed(const void *src, const float *mv, const WarpShape &s, void *out,
-                        uint8_t *mask, uint32_t *count, hipStream_t st) {
-    const FwdArgs<T> a = make_args<T>(src, mv, s, out, mask, count);
+                        uint8_t *mask, uint32_t *count, const BwdWorkspace *rec,
+                        hipStream_t st) {
+    FwdArgs<T> a = make_args<T>(src, mv, s, out, mask, count);
+    if (rec) {
+        a.boxes = reinterpret_cast<Box *>(rec->boxes);
+        a.offs = reinterpret_cast<SegOffsets *>(a.boxes + static_cast<size_t>(s.n) * s.h * a.segs);
+        a.info_words = reinterpret_cast<uint32_t *>(rec->info);
+    }
     const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(a.tiles_x) * a.tiles_y * s.n));
-    if (s.w >= 2) {
+    if (specialised(s.c, s.w)) {
         switch (s.c) {
         case 1: return launch_ck<T, 1>(a, grid, st);
         case 3: return launch_ck<T, 3>(a, grid, st);
@@ -570,10 +661,32 @@ hipError_t launch_forward(int dtype, const void *src, const float *mv, const War
         if (e != hipSuccess) return e;
     }
     switch (dtype) {
-    case 0: return launch_typed<float>(src, mv, s, out, mask, count, stream);
-    case 1: return launch_typed<_Float16>(src, mv, s, out, mask, count, stream);
-    default: return launch_typed<__bf16>(src, mv, s, out, mask, count, stream);
+    case 0: return launch_typed<float>(src, mv, s, out, mask, count, nullptr, stream);
+    case 1: return launch_typed<_Float16>(src, mv, s, out, mask, count, nullptr, stream);
+    default: return launch_typed<__bf16>(src, mv, s, out, mask, count, nullptr, stream);
     }
+}
+
+hipError_t launch_forward_record(int dtype, const void *src, const float *mv, const WarpShape &s,
+                                 void *out, uint8_t *mask, uint32_t *count,
+                                 const BwdWorkspace &ws, hipStream_t stream) {
+    if (!backward_uses_footprint(s.c) || !specialised(s.c, s.w)) {
+        // the adjoint reads no records, or the kernel that serves this shape
+        // does not write them: the plain forward, then the footprint pass
+        hipError_t e = launch_forward(dtype, src, mv, s, out, mask, count, stream);
+        if (e != hipSuccess || !backward_uses_footprint(s.c)) return e;
+        return launch_footprint(mv, s, ws, stream);
+    }
+    hipError_t e = count ? launch_zero_u32(count, static_cast<int64_t>(s.n) * s.k, stream)
+                         : hipSuccess;
+    if (e != hipSuccess) return e;
+    switch (dtype) {
+    case 0: e = launch_typed<float>(src, mv, s, out, mask, count, &ws, stream); break;
+    case 1: e = launch_typed<_Float16>(src, mv, s, out, mask, count, &ws, stream); break;
+    default: e = launch_typed<__bf16>(src, mv, s, out, mask, count, &ws, stream); break;
+    }
+    if (e != hipSuccess) return e;
+    return launch_frame_reach(s, ws, stream);
 }
 
 }  // namespace exw

@@ -124,6 +124,65 @@ def test_backward_rejects(kwargs, status, needle):
     assert needle in _capi.last_error()
 
 
+def fwd_rec(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=None, k=1,
+            out=FAKE + (2 << 30), mask=None, count=None, ws=FAKE + (6 << 30), ws_bytes=1 << 30):
+    if phases is None:
+        phases = _phases(1.0)
+    return _capi.lib().exw_warp_forward_batched_record(src, dtype, n, c, h, w, mv, phases, k, out,
+                                                       mask, count, ws, ws_bytes, None)
+
+
+def bwd_rec(**kwargs):
+    a = dict(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=_phases(1.0), k=1,
+             gout=FAKE + (2 << 30), gsrc=FAKE + (3 << 30), gmv=FAKE + (4 << 30),
+             ws=FAKE + (6 << 30), ws_bytes=1 << 30)
+    a.update(kwargs)
+    return _capi.lib().exw_warp_backward_batched_recorded(
+        a["src"], a["dtype"], a["n"], a["c"], a["h"], a["w"], a["mv"], a["phases"], a["k"],
+        a["gout"], a["gsrc"], a["gmv"], a["ws"], a["ws_bytes"], None)
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(dtype=5), INVALID, "dtype"),
+    (dict(c=65), UNSUPPORTED, "channel"),
+    (dict(src=None), INVALID, "src is NULL"),
+    (dict(out=FAKE + 100), INVALID, "overlaps input src"),
+    (dict(ws=None), INVALID, "workspace is NULL"),
+    (dict(ws_bytes=16), INVALID, "needs"),
+    (dict(dtype=1, ws_bytes=1000), INVALID, "needs"),
+    (dict(ws=FAKE + (6 << 30) + 64), INVALID, "256-byte aligned"),
+    (dict(ws=FAKE + (2 << 30)), INVALID, "overlaps output workspace"),
+    (dict(ws=FAKE), INVALID, "workspace overlaps input src"),
+    (dict(mask=FAKE + (6 << 30) + 64), INVALID, "mask overlaps output workspace"),
+])
+def test_recording_forward_rejects(kwargs, status, needle):
+    st = fwd_rec(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(dtype=3), INVALID, "dtype"),
+    (dict(gout=None), INVALID, "grad_out is NULL"),
+    (dict(ws=None), INVALID, "workspace is NULL"),
+    (dict(dtype=2, ws_bytes=16), INVALID, "needs"),
+    (dict(ws=FAKE + (6 << 30) + 128), INVALID, "256-byte aligned"),
+    (dict(gsrc=FAKE + (2 << 30)), INVALID, "grad_src overlaps input grad_out"),
+])
+def test_recorded_backward_rejects(kwargs, status, needle):
+    st = bwd_rec(**kwargs)
+    assert st == status, (_capi.status_string(st), _capi.last_error())
+    assert needle in _capi.last_error()
+
+
+def test_recording_pair_on_empty_batches_is_a_no_op():
+    assert fwd_rec(n=0, src=None, mv=None, out=None, ws=None, ws_bytes=0) == 0
+    assert fwd_rec(w=0, src=None, mv=None, out=None, ws=None, ws_bytes=0) == 0
+    assert _capi.last_error() == ""
+    assert bwd_rec(n=0, src=None, mv=None, gout=None, gsrc=None, gmv=None, ws=None) == 0
+    assert bwd_rec(gsrc=None, gmv=None) == 0
+
+
 def test_empty_batches_and_no_requested_gradient_are_no_ops():
     # No pointer is needed, and nothing is launched (this host has no GPU).
     assert fwd(n=0, src=None, mv=None, out=None) == 0
