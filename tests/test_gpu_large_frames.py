@@ -5,8 +5,10 @@ uniform motion-gradient gathers address the whole frame with 32-bit offsets;
 at 4 GiB and above both fall back to per-plane addressing. This case checks
 that fallback, with rigid motion (uniform segments), a block moving
 differently (segment edges) and the frame borders, on sampled pixels: the
-forward values, mask and counts, the motion gradient, and the image gradient.
-About 21 GiB of device memory and 30 GiB of host memory.
+forward values, mask and counts, the motion gradient, and the image gradient;
+then the training pair (recording forward, adjoint from the records) on the
+same buffers against those results. About 21 GiB of device memory and 30 GiB
+of host memory.
 """
 
 import numpy as np
@@ -49,6 +51,23 @@ def test_frame_of_4gib():
     got_mask = mask[0, 0][yd, xd].cpu().numpy()
     got_gm = to_host(gm[0][:, yd, xd])
     got_gs = to_host(gs[0][:, yd[:60], xd[:60]])
+    cnt_plain = cnt.clone()
+
+    # the training pair on the same buffers: the forward records the footprint
+    # (one-pixel paths only at this size), the adjoint takes it from there
+    announce("4 GiB frame: recording forward and recorded adjoint")
+    ws = torch.empty(exw.exw_warp_backward_workspace_bytes(torch.float32, 1, c, h, w),
+                     dtype=torch.uint8, device=dev)
+    exw.exw_warp_forward_batched_record(src, mv, (phase,), out, ws, mask, cnt)
+    exw.exw_warp_backward_batched_recorded(src, mv, (phase,), g, gs, gm, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(cnt, cnt_plain)
+    assert np.array_equal(to_host(out[0, 0][:, yd, xd]), got)
+    assert np.array_equal(mask[0, 0][yd, xd].cpu().numpy(), got_mask)
+    assert np.array_equal(to_host(gm[0][:, yd, xd]), got_gm)
+    rec_gs = to_host(gs[0][:, yd[:60], xd[:60]])
+    assert float((np.abs(rec_gs - got_gs) / np.maximum(1.0, np.abs(got_gs))).max()) <= GRAD_TOL
+    del ws
 
     src_h = src[0].cpu().numpy()
     mv_h = mv[0].cpu().numpy()
