@@ -109,7 +109,9 @@ class WarpFunction(torch.autograd.Function):
         ctx.ws = None
         if ctx.needs_input_grad[0]:
             # the image gradient will be needed: the forward also records the
-            # adjoint's footprint, and the backward skips that pass
+            # adjoint's footprint, and the backward skips that pass (the
+            # workspace, which for 16-bit frames includes the adjoint's float32
+            # accumulator, is held from here to the backward)
             nbytes = exw_warp_backward_workspace_bytes(src.dtype, n, c, h, w)
             ctx.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=src.device)
             exw_warp_forward_batched_record(src, mv, phases, out, ctx.ws)

@@ -12,6 +12,9 @@
 //     when every lane shares them ("uniform" segments: rigid motion), plus
 //     the per-frame largest distance between a segment and its box (one
 //     wavefront per 16 rows of a 64-pixel column; reads the motion once).
+//     In a training step the recording forward has already written these
+//     records (footprint.h; the per-frame figures by frame_reach_kernel)
+//     and this pass is skipped.
 //   pass 2 (tiles): one wavefront owns a 128 x TH tile of the image gradient
 //     in LDS. It walks the segments whose boxes reach the tile (only those
 //     within the per-frame distance can), recomputes their taps, accumulates

@@ -20,7 +20,9 @@
 // traffic equals the algorithmic bytes (the L2 serves the overlap between
 // tiles), so the taps are gathered from global memory; an LDS-staged variant
 // and four pixels per lane were both measured slower. No MFMA: this is a
-// gather.
+// gather. The recording instantiation (REC) also writes the adjoint's
+// footprint records of its two 64-pixel segments (footprint.h), so that the
+// adjoint of a training step can skip its first pass.
 #include "footprint.h"
 #include "launch.h"
 #include "warp_common.h"
