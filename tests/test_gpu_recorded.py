@@ -164,19 +164,34 @@ def test_recorded_pair_full_size_workload():
     assert float(err.max()) <= GRAD_TOL
 
 
-def test_autograd_uses_the_recorded_pair():
+def test_autograd_uses_the_recorded_pair(monkeypatch):
     """warp_differentiable records in its forward and skips the footprint pass
     in its backward: gradients equal those of the plain adjoint."""
     dev = need_gpu()
     d = make_config(2, n=2, h=75, w=131)
     phases = list(d["phases"])
+    calls = []
+    rec_fwd, bwd = exw.exw_warp_forward_batched_record, exw.exw_warp_backward_batched
+
+    def spy_fwd(*args, **kwargs):
+        calls.append("record")
+        return rec_fwd(*args, **kwargs)
+
+    def spy_bwd(*args, **kwargs):
+        calls.append("recorded" if kwargs.get("recorded") else "plain")
+        return bwd(*args, **kwargs)
+
+    monkeypatch.setattr(exw, "exw_warp_forward_batched_record", spy_fwd)
+    monkeypatch.setattr(exw, "exw_warp_backward_batched", spy_bwd)
     for dtype in ("f32", "f16"):
         announce("recorded: autograd", dtype)
         src = to_dev(d["src"], dtype, dev).requires_grad_(True)
         mv = torch.from_numpy(d["mv"]).to(dev).requires_grad_(True)
+        calls.clear()
         out = exw.warp_differentiable(src, mv, phases)
         wgt = torch.linspace(-1, 1, out.numel(), device=dev).reshape(out.shape).to(out.dtype)
         (out.float() * wgt.float()).sum().backward()
+        assert calls == ["record", "recorded"], calls
         gs, gm = exw.warp_backward(src.detach(), mv.detach(), phases, wgt)
         assert torch.equal(out.detach(), exw.warp(src.detach(), mv.detach(), phases))
         assert torch.equal(mv.grad, gm)
