@@ -140,9 +140,9 @@ size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, 
  * contributions of the output pixels whose taps land there (LDS
  * accumulation, plain stores); output segments whose taps lie more than 128
  * px away fall back to float32 atomics. The summation order is fixed except
- * where atomics are used (taps at motion boundaries are added with LDS
- * atomics, far segments with global ones), so the last bits of grad_src can
- * differ from run to run.
+ * where atomics are used (taps at motion boundaries of frames with 1, 2, 4
+ * or 12 channels are added with LDS atomics, far segments with global ones),
+ * so the last bits of grad_src can differ from run to run.
  */
 exw_status exw_warp_backward_batched(const void *src, exw_dtype dtype, int32_t n, int32_t c,
                                      int32_t h, int32_t w, const float *mv, const float *phases,

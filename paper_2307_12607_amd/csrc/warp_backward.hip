@@ -290,8 +290,10 @@ struct SegLoad {
 // for every lane, so a row outside the tile is skipped by the whole wavefront;
 // lanes whose column lies outside the tile read a cell but do not write it.
 // Lanes with another offset (motion boundaries, random motion) add their taps
-// with LDS atomics, which serialise per lane on this hardware; the uniform path
-// must carry the bulk of the work.
+// one at a time: where a cell has a spare word (three channels in four) by
+// whole-cell read-add-writes that colliding lanes take in turns, otherwise by
+// LDS atomics, one per channel, which serialise per lane on this hardware;
+// the uniform path must carry the bulk of the work.
 //
 // Uniform segments (pass 1 found every lane valid with one offset per phase)
 // skip the per-lane split, the pattern search and the atomics, and gather the
@@ -617,8 +619,48 @@ __global__ __launch_bounds__(kSegW) void adjoint_tiles_kernel(BwdArgs<T> a) {
             for (int ch = 0; ch < CT; ++ch) gg[ch] = uni ? g[k][ch] : 0.0f;
             const float fx = t[k].ax.f, fy = t[k].ay.f;
             scatter_pattern(x - rx - tx0, y - ry - ty0, fx, fy, gg);
-            // Lanes off the uniform pattern (motion boundaries): LDS atomics.
-            if (__ballot(any && !uni)) {
+            // Lanes off the uniform pattern (motion boundaries, random motion).
+            if constexpr (CP > CT) {
+                // Cells have a spare word: whole-cell read-add-writes, one tap
+                // position at a time. Lanes whose cells coincide take turns:
+                // each writes its lane number into the cell's spare word and
+                // the lane that reads its own number back adds its tap this
+                // round (LDS accesses of one wavefront complete in order; every
+                // round retires at least one lane per contested cell). One
+                // read-add-write covers all channels, where atomics take one
+                // per channel, and the order of the additions is fixed.
+                const bool off = any && !uni;
+                if (__ballot(off)) {
+                    const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
+                    const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
+                    const int lx1 = t[k].ax.i1 - tx0, ly1 = t[k].ay.i1 - ty0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int lx = (q & 1) ? lx1 : lx0, ly = (q & 2) ? ly1 : ly0;
+                        const float wq = q == 0 ? w00 : (q == 1 ? w01 : (q == 2 ? w10 : w11));
+                        bool pend = off && (unsigned)lx < (unsigned)kTileW &&
+                                    (unsigned)ly < (unsigned)TH && wq != 0.0f;
+                        const int cell = pend ? ly * kTileW + lx : 0;
+                        // (atomic accesses: the read must not be served from
+                        // this lane's own store)
+                        int *own = reinterpret_cast<int *>(acc) + cell * CP + (CP - 1);
+                        while (__ballot(pend)) {  // wave-uniform
+                            if (pend)
+                                __hip_atomic_store(own, lane, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            if (pend && __hip_atomic_load(own, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP) == lane) {
+                                float c[CP];
+                                cell_read<CP>(acc, cell, c);
+#pragma unroll
+                                for (int ch = 0; ch < CT; ++ch) c[ch] = fmaf(wq, g[k][ch], c[ch]);
+                                cell_write<CP>(acc, cell, c);
+                                pend = false;
+                            }
+                        }
+                    }
+                }
+            } else if (__ballot(any && !uni)) {  // LDS atomics
                 if (any && !uni) {
                     const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy);
                     const float w10 = (1.0f - fx) * fy, w11 = fx * fy;
