@@ -128,19 +128,23 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
 }
 
 // Per-frame figures from recorded boxes: what the footprint pass accumulates
-// as it goes, for boxes the forward recorded. Blocks (y: frame) take
-// kReachPerThread segments per thread, all loads in flight at once, reduce
-// through LDS and update the frame once per block (updates of one address
-// serialise: few of them, and no wavefront waits on more than one).
+// as it goes, for boxes the forward recorded. Each frame gets
+// blocks_per_frame consecutive blocks of a 1-D grid (frames can outnumber the
+// 65535 blocks a second grid dimension allows); a block takes
+// kReachPerThread segments per thread, all loads in flight at once, reduces
+// through LDS and updates the frame once (updates of one address serialise:
+// few of them, and no wavefront waits on more than one).
 constexpr int kReachPerThread = 4;
 
 __global__ __launch_bounds__(kThreads) void frame_reach_kernel(const Box *boxes, FrameInfo *info,
-                                                               int h, int segs) {
+                                                               int h, int segs,
+                                                               int blocks_per_frame) {
     __shared__ int red[2][kThreads / kSegW];
-    const int in = blockIdx.y;
+    const int in = static_cast<int>(blockIdx.x) / blocks_per_frame;
+    const int part = static_cast<int>(blockIdx.x) - in * blocks_per_frame;
     const int per_frame = h * segs;  // below 2^31: the C ABI bounds H * W
     const Box *fb = boxes + static_cast<int64_t>(in) * per_frame;
-    const int i0 = blockIdx.x * (kThreads * kReachPerThread) + threadIdx.x;
+    const int i0 = part * (kThreads * kReachPerThread) + threadIdx.x;
     Box bx[kReachPerThread];
 #pragma unroll
     for (int j = 0; j < kReachPerThread; ++j) {
@@ -1045,11 +1049,12 @@ bool backward_uses_footprint(int c) { return c == 1 || c == 2 || c == 3 || c == 
 hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, hipStream_t stream) {
     const int segs = (s.w + kSegW - 1) / kSegW;
     const int64_t per_frame = static_cast<int64_t>(s.h) * segs;
-    const unsigned bx = static_cast<unsigned>((per_frame + kThreads * kReachPerThread - 1) /
-                                              (kThreads * kReachPerThread));
-    hipLaunchKernelGGL(frame_reach_kernel, dim3(bx, static_cast<unsigned>(s.n)), dim3(kThreads), 0,
-                       stream, reinterpret_cast<const Box *>(ws.boxes),
-                       reinterpret_cast<FrameInfo *>(ws.info), s.h, segs);
+    const int bx = static_cast<int>((per_frame + kThreads * kReachPerThread - 1) /
+                                    (kThreads * kReachPerThread));
+    // n * bx < 2^31: the C ABI bounds the batch's 64 x 4 tiles below 2^31
+    hipLaunchKernelGGL(frame_reach_kernel, dim3(static_cast<unsigned>(static_cast<int64_t>(s.n) * bx)),
+                       dim3(kThreads), 0, stream, reinterpret_cast<const Box *>(ws.boxes),
+                       reinterpret_cast<FrameInfo *>(ws.info), s.h, segs, bx);
     return hipGetLastError();
 }
 

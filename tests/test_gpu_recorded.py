@@ -197,3 +197,41 @@ def test_autograd_uses_the_recorded_pair(monkeypatch):
         assert torch.equal(mv.grad, gm)
         tol = 1e-5 if dtype == "f32" else 2e-3
         assert torch.allclose(src.grad.float(), gs.float(), rtol=tol, atol=tol)
+
+
+def test_recorded_pair_many_small_frames():
+    """More frames than a second grid dimension could hold (70000 frames of
+    5 x 7 px, random motion): the training pair's records, outputs and
+    gradients against the plain calls, and three frames against the oracle."""
+    dev = need_gpu()
+    n, c, h, w, phases = 70000, 3, 5, 7, (0.5, 1.0)
+    k = len(phases)
+    rng = np.random.default_rng(21)
+    src = rng.random((n, c, h, w), dtype=np.float32)
+    mv = rng.uniform(-3, 3, (n, 2, h, w)).astype(np.float32)
+    g = rng.standard_normal((n, k, c, h, w)).astype(np.float32)
+    s, m, gd = (torch.from_numpy(a).to(dev) for a in (src, mv, g))
+    nbytes = exw.exw_warp_backward_workspace_bytes(torch.float32, n, c, h, w)
+    announce("recorded: 70000 small frames")
+    outs = [torch.empty((n, k, c, h, w), device=dev) for _ in range(2)]
+    masks = [torch.empty((n, k, h, w), dtype=torch.uint8, device=dev) for _ in range(2)]
+    cnts = [torch.empty((n, k), dtype=torch.int32, device=dev) for _ in range(2)]
+    wss = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+    gss = [torch.empty_like(s) for _ in range(2)]
+    gms = [torch.empty((n, 2, h, w), device=dev) for _ in range(2)]
+    exw.exw_warp_forward_batched(s, m, phases, outs[0], masks[0], cnts[0])
+    exw.exw_warp_backward_batched(s, m, phases, gd, gss[0], gms[0], wss[0])
+    exw.exw_warp_forward_batched_record(s, m, phases, outs[1], wss[1], masks[1], cnts[1])
+    exw.exw_warp_backward_batched_recorded(s, m, phases, gd, gss[1], gms[1], wss[1])
+    torch.cuda.synchronize()
+    r0, r1 = records(wss[0], n, h, w), records(wss[1], n, h, w)
+    assert np.array_equal(r0["segments"], r1["segments"])
+    assert np.array_equal(r0["frames"], r1["frames"])
+    assert torch.equal(outs[0], outs[1]) and torch.equal(masks[0], masks[1])
+    assert torch.equal(cnts[0], cnts[1]) and torch.equal(gms[0], gms[1])
+    err = ((gss[1] - gss[0]).abs() / gss[0].abs().clamp(min=1.0)).max().item()
+    assert err <= GRAD_TOL, err
+    pick = [0, 65536, n - 1]
+    ref_gs, ref_gm = warp_oracle.backward(src[pick], mv[pick], list(phases), g[pick])
+    for got, ref in ((to_host(gss[1][pick]), ref_gs), (to_host(gms[1][pick]), ref_gm)):
+        assert float((np.abs(got - ref) / np.maximum(1.0, np.abs(ref))).max()) <= GRAD_TOL
