@@ -737,8 +737,12 @@ __global__ __launch_bounds__(kThreads) void adjoint_far_kernel(BwdArgs<T> a, flo
     const int lane = threadIdx.x % kSegW;
     const int64_t hw = static_cast<int64_t>(h) * w;
     const int64_t per_frame = static_cast<int64_t>(h) * a.segs;
-    for (int in = 0; in < a.n; ++in) {
-        if (!a.info[in].has_far) continue;  // uniform across the grid
+    // The frames' far flags, 64 at a time (one load and a ballot per 64
+    // frames, not a chain of one load per frame); then the flagged frames.
+    for (int f0 = 0; f0 < a.n; f0 += kSegW)
+    for (unsigned long long fm = __ballot(f0 + lane < a.n && a.info[f0 + lane].has_far != 0); fm;
+         fm &= fm - 1) {
+        const int in = f0 + __builtin_ctzll(fm);  // uniform across the grid
         float *acc = accum + static_cast<int64_t>(in) * C * hw;
         for (int64_t sg = static_cast<int64_t>(blockIdx.x) * (kThreads / kSegW) + wave;
              sg < per_frame; sg += static_cast<int64_t>(gridDim.x) * (kThreads / kSegW)) {
@@ -782,8 +786,11 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void cast_far_frames_kernel(const float *accum32, T *gsrc,
                                                                    const FrameInfo *info, int n,
                                                                    int64_t frame_elems) {
-    for (int in = 0; in < n; ++in) {
-        if (!info[in].has_far) continue;
+    const int lane = threadIdx.x % kSegW;
+    for (int f0 = 0; f0 < n; f0 += kSegW)  // far flags 64 at a time, as in pass 3
+    for (unsigned long long fm = __ballot(f0 + lane < n && info[f0 + lane].has_far != 0); fm;
+         fm &= fm - 1) {
+        const int in = f0 + __builtin_ctzll(fm);
         const float *s = accum32 + static_cast<int64_t>(in) * frame_elems;
         T *d = gsrc + static_cast<int64_t>(in) * frame_elems;
         for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
