@@ -193,7 +193,7 @@ exw_status exw_warp_backward_batched_recorded(const void *src, exw_dtype dtype, 
 /* ------------------------------------------------------------------------
  * Scene-state statistics that accompany a warp.
  *
- * Paper §V: the state the warp/extrapolate decision is taken on includes the
+ * Paper §IV-C (Eq. 1): the state the warp/extrapolate decision is taken on includes the
  * variance of the motion-vector buffer, horizontally and vertically
  * (Var_x(F_mv), Var_y(F_mv) in the environment vector E_t; Table IV lists the
  * motion variance as the feature that reveals dynamic objects). Here it is
@@ -229,7 +229,7 @@ exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, do
 /* ------------------------------------------------------------------------
  * Frame quality.
  *
- * Paper §V: the reward of the warp/extrapolate decision is the gain in PSNR
+ * Paper §IV-C1: the reward of the warp/extrapolate decision is the gain in PSNR
  * (10 log10(peak^2 / MSE)) and in SSIM of the frame an action produces over
  * the frame the other action would have produced, both against the ground
  * truth.
@@ -309,7 +309,7 @@ exw_status exw_decision_plan(int32_t d1, int32_t d2, int32_t d_last, exw_display
 
 /*
  * A fixed policy for the three decisions of one frame (a stand-in for the
- * paper's learned predictor, §V, which needs trained weights): warp at a
+ * paper's learned predictor, §IV-C, which needs trained weights): warp at a
  * node when Var_x + Var_y of the frame's motion (motion_stats[1] +
  * motion_stats[3], the layout of exw_motion_stats) is at most max_variance
  * and the out-of-frame fraction of the warp that node would show is at most

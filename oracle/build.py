@@ -11,7 +11,10 @@ SRC = os.path.join(HERE, "warp_ref.c")
 LIB = os.path.join(HERE, "libwarp_ref.so")
 
 # Baseline x86-64 code: the library is built here and may run on another host.
-CFLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
+# -O2, not -O3: gcc 11.4's -O3 loop vectorizer dropped the float32 rounding of
+# the displacement (the (double)(float) conversion under the exact-mode test),
+# which the mask pins at phase 3/4 catch.
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
           "-Wextra"]
 
 

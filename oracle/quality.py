@@ -1,6 +1,6 @@
 """Float64 oracle of the frame-quality measures (test infrastructure only).
 
-What is computed (paper §V, the reward of the decision predictor): the gain
+What is computed (paper §IV-C1, the reward of the decision predictor): the gain
 in PSNR and SSIM of the frame an action produces over the frame the other
 action would have produced, both measured against the ground-truth frame.
 PSNR is 10 log10(peak^2 / MSE) with the 8-bit peak 255 in the paper; SSIM is
@@ -50,7 +50,7 @@ def mse(a, b) -> float:
 
 
 def psnr(a, b, peak: float = 1.0) -> float:
-    """10 log10(peak^2 / MSE) of one frame (§V); +inf for identical frames."""
+    """10 log10(peak^2 / MSE) of one frame (§IV-C1); +inf for identical frames."""
     m = mse(a, b)
     return math.inf if m == 0.0 else 10.0 * math.log10(peak * peak / m)
 

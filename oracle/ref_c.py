@@ -24,9 +24,9 @@ def lib():
         L = ctypes.CDLL(LIB)
         i64 = ctypes.c_int64
         p = ctypes.c_void_p
-        L.warp_ref_forward.argtypes = [p, p, i64, i64, i64, i64, p, i64, p, p, p]
+        L.warp_ref_forward.argtypes = [p, p, i64, i64, i64, i64, p, i64, p, p, p, ctypes.c_int]
         L.warp_ref_forward.restype = ctypes.c_int
-        L.warp_ref_backward.argtypes = [p, p, i64, i64, i64, i64, p, i64, p, p, p]
+        L.warp_ref_backward.argtypes = [p, p, i64, i64, i64, i64, p, i64, p, p, p, ctypes.c_int]
         L.warp_ref_backward.restype = ctypes.c_int
         L.warp_ref_max_threads.restype = ctypes.c_int
         L.warp_ref_set_threads.argtypes = [ctypes.c_int]
@@ -53,8 +53,11 @@ def prepare(src, mv, phases):
             np.ascontiguousarray(np.asarray(phases, dtype=np.float32).reshape(-1)))
 
 
-def forward(src, mv, phases):
-    """Returns ``(out [N,K,C,H,W] f64, mask [N,K,H,W] u8, invalid_count [N,K] i64)``."""
+def forward(src, mv, phases, exact: bool = False):
+    """Returns ``(out [N,K,C,H,W] f64, mask [N,K,H,W] u8, invalid_count [N,K] i64)``.
+
+    ``exact``: the displacement s*u exactly (float64), else rounded once to
+    float32 (see ``warp_ref.c``)."""
     s, m, ph = prepare(src, mv, phases)
     n, c, h, w = s.shape
     k = ph.size
@@ -62,37 +65,37 @@ def forward(src, mv, phases):
     mask = np.empty((n, k, h, w), dtype=np.uint8)
     cnt = np.empty((n, k), dtype=np.int64)
     rc = lib().warp_ref_forward(_ptr(s), _ptr(m), n, c, h, w, _ptr(ph), k, _ptr(out), _ptr(mask),
-                                _ptr(cnt))
+                                _ptr(cnt), int(bool(exact)))
     if rc != 0:
         raise ValueError("warp_ref_forward rejected its arguments")
     return out, mask, cnt
 
 
-def forward_prepared(s, m, ph, out, mask, cnt):
+def forward_prepared(s, m, ph, out, mask, cnt, exact: bool = False):
     """Forward on already-converted buffers (used to time the oracle alone)."""
     n, c, h, w = s.shape
     rc = lib().warp_ref_forward(_ptr(s), _ptr(m), n, c, h, w, _ptr(ph), ph.size, _ptr(out),
-                                _ptr(mask), _ptr(cnt))
+                                _ptr(mask), _ptr(cnt), int(bool(exact)))
     if rc != 0:
         raise ValueError("warp_ref_forward rejected its arguments")
 
 
-def backward(src, mv, phases, grad_out):
+def backward(src, mv, phases, grad_out, exact: bool = False):
     """Returns ``(grad_src [N,C,H,W] f64, grad_mv [N,2,H,W] f64)``."""
     s, m, ph = prepare(src, mv, phases)
     g = np.ascontiguousarray(np.asarray(grad_out).astype(np.float64))
     n, c, h, w = s.shape
     gs = np.empty_like(s)
     gm = np.empty((n, 2, h, w), dtype=np.float64)
-    backward_prepared(s, m, ph, g, gs, gm)
+    backward_prepared(s, m, ph, g, gs, gm, exact)
     return gs, gm
 
 
-def backward_prepared(s, m, ph, g, gs, gm):
+def backward_prepared(s, m, ph, g, gs, gm, exact: bool = False):
     n, c, h, w = s.shape
     if g.shape != (n, ph.size, c, h, w):
         raise ValueError("grad_out shape mismatch")
     rc = lib().warp_ref_backward(_ptr(s), _ptr(m), n, c, h, w, _ptr(ph), ph.size, _ptr(g),
-                                 _ptr(gs), _ptr(gm))
+                                 _ptr(gs), _ptr(gm), int(bool(exact)))
     if rc != 0:
         raise ValueError("warp_ref_backward rejected its arguments")

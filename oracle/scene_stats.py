@@ -1,6 +1,6 @@
 """Float64 oracle of the per-frame scene-state statistics (test infrastructure only).
 
-What is computed (paper §V, the environment vector E_t of a frame F_t): the
+What is computed (paper §IV-C, Eq. 1: the environment vector E_t of a frame F_t): the
 variance of the motion-vector buffer, taken separately for the horizontal
 and the vertical component (Var_x(F_mv), Var_y(F_mv); Table IV lists the
 motion variance as the feature that reveals dynamic objects, §III-D), and
@@ -46,7 +46,7 @@ def _mean_var(values: np.ndarray) -> tuple[float, float]:
 
 
 def motion_stats(mv) -> np.ndarray:
-    """Per-frame motion statistics (§V, E_t: Var_x(F_mv), Var_y(F_mv)).
+    """Per-frame motion statistics (§IV-C, Eq. 1, E_t: Var_x(F_mv), Var_y(F_mv)).
 
     ``mv`` is [N, 2, H, W] (component 0 horizontal, 1 vertical) or [2, H, W].
     Returns float64 [N, 4] = (mean_x, var_x, mean_y, var_y) per frame.
@@ -64,7 +64,7 @@ def motion_stats(mv) -> np.ndarray:
 
 
 def resolution(h: int, w: int) -> int:
-    """Rendering resolution R = R_h x R_w as one integer (§V, E_t)."""
+    """Rendering resolution R = R_h x R_w as one integer (§IV-C, Eq. 1, E_t)."""
     return int(h) * int(w)
 
 

@@ -23,11 +23,16 @@ are:
   invalid. The test is evaluated exactly (on the displacement against integer
   bounds), and the cell as ``x0 = x - ceil(d)`` with fraction ``ceil(d) - d``,
   so that a displacement far below an ulp of x is not rounded away.
-* The displacement ``s*u`` is rounded once to float32, the precision of the
-  motion field, so the validity decision is taken in the same precision on
-  every implementation. For phases 0, 1/4, 1/2 and 1 the product is exact, so
-  this is the exact definition; for 3/4 it differs by at most 2^-24 relative.
-  Everything after that rounding is exact or float64.
+* Two modes for the displacement ``d = s*u``. The exact mode
+  (``exact=True``) is the plain definition: ``s*u`` in float64, which is
+  exact because ``s`` and ``u`` are float32 (a product of two 24-bit
+  significands fits in 53 bits). The default mode rounds ``s*u`` once to
+  float32, the precision of the motion field, so that the validity decision
+  is taken in the precision a float32 implementation takes it in. For phases
+  0, 1/4, 1/2 and 1 the product is exact and the two modes agree; for 3/4
+  they differ by at most 2^-24 relative in ``d``, so a mask can differ only
+  where the exact sample point lies within half a float32 ulp of ``d`` from a
+  frame bound. Everything after the displacement is exact or float64.
 * Backward pass: the transpose of the bilinear gather for the image, and the
   derivative of the bilinear blend along the sampling coordinate for the
   motion, using the right-derivative at the floor kinks; summed over phases;
@@ -42,19 +47,22 @@ from __future__ import annotations
 import numpy as np
 
 
-def displacement(comp: np.ndarray, phase: float) -> np.ndarray:
-    """``s * mv`` rounded once to float32, returned as float64.
+def displacement(comp: np.ndarray, phase: float, exact: bool = False) -> np.ndarray:
+    """``s * mv`` as float64: exact, or rounded once to float32.
 
-    The product of two float32 numbers is exact in float64, so rounding it to
-    float32 gives the correctly rounded float32 product.
+    The product of two float32 numbers is exact in float64, so it is the exact
+    displacement, and rounding it to float32 gives the correctly rounded
+    float32 product.
     """
     s = np.float64(np.float32(phase))
     prod = s * np.asarray(comp, dtype=np.float32).astype(np.float64)
+    if exact:
+        return prod
     return prod.astype(np.float32).astype(np.float64)
 
 
 def taps(u: np.ndarray, v: np.ndarray, phase: float, xs: np.ndarray, ys: np.ndarray,
-         h: int, w: int):
+         h: int, w: int, exact: bool = False):
     """Bilinear taps of the output pixels ``(xs, ys)`` whose motion is ``(u, v)``.
 
     Returns ``valid, x0, x1, y0, y1, fx, fy`` (arrays shaped like ``xs``);
@@ -62,8 +70,8 @@ def taps(u: np.ndarray, v: np.ndarray, phase: float, xs: np.ndarray, ys: np.ndar
     """
     xs = np.asarray(xs, dtype=np.int64)
     ys = np.asarray(ys, dtype=np.int64)
-    dx = displacement(u, phase)
-    dy = displacement(v, phase)
+    dx = displacement(u, phase, exact)
+    dy = displacement(v, phase, exact)
     # 0 <= x - d <= W-1, stated on d against integer bounds: exact even where
     # |d| is below half an ulp of x and forming x - d would round.
     with np.errstate(invalid="ignore"):
@@ -86,7 +94,7 @@ def _as_f64(a) -> np.ndarray:
     return np.asarray(a).astype(np.float64)
 
 
-def sample(img: np.ndarray, u, v, phase: float, xs, ys):
+def sample(img: np.ndarray, u, v, phase: float, xs, ys, exact: bool = False):
     """Warp of one frame ``img`` [C, H, W] at output pixels ``(xs, ys)``.
 
     ``u, v`` are the motion components at those output pixels. Returns
@@ -95,7 +103,7 @@ def sample(img: np.ndarray, u, v, phase: float, xs, ys):
     img = _as_f64(img)
     h, w = img.shape[-2:]
     valid, x0, x1, y0, y1, fx, fy = taps(np.ravel(u), np.ravel(v), phase, np.ravel(xs),
-                                         np.ravel(ys), h, w)
+                                         np.ravel(ys), h, w, exact)
     i00 = img[:, y0, x0]
     i01 = img[:, y0, x1]
     i10 = img[:, y1, x0]
@@ -105,7 +113,7 @@ def sample(img: np.ndarray, u, v, phase: float, xs, ys):
     return np.where(valid, val, 0.0), valid
 
 
-def forward(src, mv, phases):
+def forward(src, mv, phases, exact: bool = False):
     """Warp every frame at every phase.
 
     ``src`` [N, C, H, W] (any float dtype: the stored values are upcast),
@@ -124,14 +132,14 @@ def forward(src, mv, phases):
     count = np.zeros((n, k), dtype=np.int64)
     for i in range(n):
         for j in range(k):
-            val, valid = sample(src[i], mv[i, 0], mv[i, 1], phases[j], xs, ys)
+            val, valid = sample(src[i], mv[i, 0], mv[i, 1], phases[j], xs, ys, exact)
             out[i, j] = val.reshape(c, h, w)
             mask[i, j] = valid.reshape(h, w)
             count[i, j] = valid.size - int(valid.sum())
     return out, mask, count
 
 
-def backward(src, mv, phases, grad_out):
+def backward(src, mv, phases, grad_out, exact: bool = False):
     """Gradients of ``sum(grad_out * forward(src, mv, phases)[0])``.
 
     Returns ``grad_src`` [N, C, H, W] and ``grad_mv`` [N, 2, H, W], float64,
@@ -151,7 +159,7 @@ def backward(src, mv, phases, grad_out):
         img = src[i]
         for j, s in enumerate(phases):
             valid, x0, x1, y0, y1, fx, fy = taps(mv[i, 0].ravel(), mv[i, 1].ravel(), s, xs, ys,
-                                                 h, w)
+                                                 h, w, exact)
             g = g_all[i, j].reshape(c, -1) * valid  # zero for invalid pixels
             # Image: transpose of the gather, one scatter per tap.
             for yy, xx, wt in ((y0, x0, (1 - fx) * (1 - fy)), (y0, x1, fx * (1 - fy)),
@@ -176,7 +184,7 @@ def backward(src, mv, phases, grad_out):
 
 # ------------------------------------------------- point-wise (sampled) forms
 
-def forward_at(src_frame, mv_frame, phase: float, ys, xs):
+def forward_at(src_frame, mv_frame, phase: float, ys, xs, exact: bool = False):
     """Outputs of one frame at one phase at the listed pixels only.
 
     ``src_frame`` [C, H, W], ``mv_frame`` [2, H, W]. Returns ``(values [C, P],
@@ -185,10 +193,10 @@ def forward_at(src_frame, mv_frame, phase: float, ys, xs):
     ys = np.asarray(ys, dtype=np.int64)
     xs = np.asarray(xs, dtype=np.int64)
     mvf = np.asarray(mv_frame, dtype=np.float32)
-    return sample(src_frame, mvf[0, ys, xs], mvf[1, ys, xs], phase, xs, ys)
+    return sample(src_frame, mvf[0, ys, xs], mvf[1, ys, xs], phase, xs, ys, exact)
 
 
-def grad_mv_at(src_frame, mv_frame, phases, grad_out_frame, ys, xs):
+def grad_mv_at(src_frame, mv_frame, phases, grad_out_frame, ys, xs, exact: bool = False):
     """``grad_mv`` of one frame at the listed pixels: [2, P] float64.
 
     ``grad_out_frame`` is [K, C, H, W]. A pixel's motion gradient depends only
@@ -201,7 +209,8 @@ def grad_mv_at(src_frame, mv_frame, phases, grad_out_frame, ys, xs):
     mvf = np.asarray(mv_frame, dtype=np.float32)
     out = np.zeros((2, ys.size), dtype=np.float64)
     for j, s in enumerate(np.asarray(phases, dtype=np.float32).reshape(-1)):
-        valid, x0, x1, y0, y1, fx, fy = taps(mvf[0, ys, xs], mvf[1, ys, xs], s, xs, ys, h, w)
+        valid, x0, x1, y0, y1, fx, fy = taps(mvf[0, ys, xs], mvf[1, ys, xs], s, xs, ys, h, w,
+                                             exact)
         g = _as_f64(grad_out_frame[j][:, ys, xs]) * valid
         d_sx = (1 - fy) * (img[:, y0, x1] - img[:, y0, x0]) + fy * (img[:, y1, x1] - img[:, y1, x0])
         d_sy = (1 - fx) * (img[:, y1, x0] - img[:, y0, x0]) + fx * (img[:, y1, x1] - img[:, y0, x1])
@@ -210,7 +219,7 @@ def grad_mv_at(src_frame, mv_frame, phases, grad_out_frame, ys, xs):
     return out
 
 
-def grad_src_at(mv_frame, phases, grad_out_frame, ys, xs, radius: int):
+def grad_src_at(mv_frame, phases, grad_out_frame, ys, xs, radius: int, exact: bool = False):
     """``grad_src`` of one frame at the listed source pixels: [C, P] float64.
 
     For each listed source pixel q, every output pixel within ``radius`` of q
@@ -233,7 +242,8 @@ def grad_src_at(mv_frame, phases, grad_out_frame, ys, xs, radius: int):
         gy = gy.ravel()
         gx = gx.ravel()
         for j, s in enumerate(phases):
-            valid, x0, x1, y0, y1, fx, fy = taps(mvf[0, gy, gx], mvf[1, gy, gx], s, gx, gy, h, w)
+            valid, x0, x1, y0, y1, fx, fy = taps(mvf[0, gy, gx], mvf[1, gy, gx], s, gx, gy, h, w,
+                                                 exact)
             wsum = np.zeros(gy.size, dtype=np.float64)
             for yy, xx, wt in ((y0, x0, (1 - fx) * (1 - fy)), (y0, x1, fx * (1 - fy)),
                                (y1, x0, (1 - fx) * fy), (y1, x1, fx * fy)):

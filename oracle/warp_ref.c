@@ -6,8 +6,11 @@
  * Definition (paper §II-B image warping; §IV-B frames P_i at t + i/4 made from
  * F_t alone; §III-B invalid pixels of a warped frame; §III-D per-pixel motion):
  * output pixel (x, y) of frame n at phase s samples F_n bilinearly at
- * (x - s*u, y - s*v), (u, v) = mv[n, :, y, x]. The displacement s*u is rounded
- * once to float32 (the motion field's precision); all later steps are float64.
+ * (x - s*u, y - s*v), (u, v) = mv[n, :, y, x]. The displacement d = s*u is
+ * either exact (exact != 0: the float64 product of the float32 phase and
+ * motion, which is exact since two 24-bit significands fit in 53 bits) or
+ * rounded once to float32 (exact == 0: the motion field's precision, the one
+ * a float32 implementation decides validity in); all later steps are float64.
  * Valid iff 0 <= sx <= W-1 and 0 <= sy <= H-1 (tested exactly on d); invalid
  * pixels are 0, mask 0, and are counted. Taps (x0, y0), (x1, y0), (x0, y1), (x1, y1) with
  * x0 = floor(sx), x1 = min(x0 + 1, W - 1), weights from the fractions.
@@ -32,11 +35,16 @@ typedef struct {
     double fx, fy;
 } taps_t;
 
-static taps_t make_taps(float u, float v, float s, int64_t x, int64_t y, int64_t h, int64_t w)
+static taps_t make_taps(float u, float v, float s, int64_t x, int64_t y, int64_t h, int64_t w,
+                        int exact)
 {
     taps_t t;
-    double dx = (double)(float)((double)s * (double)u);
-    double dy = (double)(float)((double)s * (double)v);
+    double dx = (double)s * (double)u;
+    double dy = (double)s * (double)v;
+    if (!exact) {
+        dx = (double)(float)dx;
+        dy = (double)(float)dy;
+    }
     memset(&t, 0, sizeof t);
     /* 0 <= x - d <= W-1 on d against integer bounds (exact even when |d| is
      * below half an ulp of x). */
@@ -76,7 +84,7 @@ void warp_ref_set_threads(int n)
 
 int warp_ref_forward(const double *src, const float *mv, int64_t n, int64_t c, int64_t h,
                      int64_t w, const float *phases, int64_t k, double *out, uint8_t *mask,
-                     int64_t *invalid_count)
+                     int64_t *invalid_count, int exact)
 {
     if (n < 0 || c < 1 || h < 1 || w < 1 || k < 1)
         return -1;
@@ -93,7 +101,7 @@ int warp_ref_forward(const double *src, const float *mv, int64_t n, int64_t c, i
                 int64_t row_invalid = 0;
                 for (int64_t x = 0; x < w; ++x) {
                     const int64_t p = y * w + x;
-                    taps_t t = make_taps(u[p], v[p], phases[ik], x, y, h, w);
+                    taps_t t = make_taps(u[p], v[p], phases[ik], x, y, h, w, exact);
                     mask[(in * k + ik) * hw + p] = (uint8_t)t.valid;
                     row_invalid += !t.valid;
                     for (int64_t ch = 0; ch < c; ++ch) {
@@ -116,7 +124,7 @@ int warp_ref_forward(const double *src, const float *mv, int64_t n, int64_t c, i
 
 int warp_ref_backward(const double *src, const float *mv, int64_t n, int64_t c, int64_t h,
                       int64_t w, const float *phases, int64_t k, const double *grad_out,
-                      double *grad_src, double *grad_mv)
+                      double *grad_src, double *grad_mv, int exact)
 {
     if (n < 0 || c < 1 || h < 1 || w < 1 || k < 1)
         return -1;
@@ -132,7 +140,7 @@ int warp_ref_backward(const double *src, const float *mv, int64_t n, int64_t c, 
                 const int64_t p = y * w + x;
                 double gu = 0.0, gv = 0.0;
                 for (int64_t ik = 0; ik < k; ++ik) {
-                    taps_t t = make_taps(u[p], v[p], phases[ik], x, y, h, w);
+                    taps_t t = make_taps(u[p], v[p], phases[ik], x, y, h, w, exact);
                     if (!t.valid)
                         continue;
                     double su = 0.0, sv = 0.0;
@@ -165,7 +173,7 @@ int warp_ref_backward(const double *src, const float *mv, int64_t n, int64_t c, 
                 for (int64_t y = 0; y < h; ++y)
                     for (int64_t x = 0; x < w; ++x) {
                         const int64_t p = y * w + x;
-                        taps_t t = make_taps(u[p], v[p], phases[ik], x, y, h, w);
+                        taps_t t = make_taps(u[p], v[p], phases[ik], x, y, h, w, exact);
                         if (!t.valid)
                             continue;
                         double g = grad_out[((in * k + ik) * c + ch) * hw + p];

@@ -11,9 +11,9 @@ package marshals torch tensors to that ABI:
 * ``WarpFunction`` / ``warp_differentiable``: autograd over the hand-written
   adjoint (gradients for the frames and the motion vectors).
 * ``motion_stats``: per-frame mean and variance of the motion field, the
-  scene-state feature the warp/extrapolate decision is taken on (§V).
+  scene-state feature the warp/extrapolate decision is taken on (§IV-C, Eq. 1).
 * ``frame_quality``: per-frame MSE, PSNR and SSIM against the ground truth,
-  the quality terms of the decision's reward (§V).
+  the quality terms of the decision's reward (§IV-C1).
 * ``warp_chain``, ``plan``, ``threshold_policy``, ``decision_path_frames``:
   the decision paths of §IV-B / Table V (chained warps W(P_i) on the GPU,
   the decision tree and a fixed policy in native host code).

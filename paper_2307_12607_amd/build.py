@@ -22,7 +22,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # The displacement s*u must be rounded once; FMAs are written explicitly.
     "-ffp-contract=off",
     # Keep float32 denormals: tiny displacements must not flush to zero.
@@ -36,9 +35,30 @@ FLAGS = [
     "-Wno-pass-failed",
 ]
 
+LINK_FLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC"]
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *SOURCES, "-o", LIB + ".tmp"]
+
+OBJDIR = os.path.join(ROOT, "_build")
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to its own object (in parallel), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 8)
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        objs = list(pool.map(lambda src: _compile(src, verbose), SOURCES))
+    cmd = [HIPCC, *LINK_FLAGS, *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

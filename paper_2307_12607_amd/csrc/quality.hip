@@ -1,5 +1,5 @@
 // Frame quality on CDNA4 (gfx950): per-frame MSE, PSNR and SSIM of a
-// predicted frame against the ground truth (paper §V: the decision
+// predicted frame against the ground truth (paper §IV-C1: the decision
 // predictor's reward is the gain in PSNR = 10 log10(peak^2 / MSE) and in
 // SSIM of the chosen action's frame over the other action's frame).
 //

@@ -1,6 +1,6 @@
 // Per-frame motion statistics for CDNA4 (gfx950): mean and population
 // variance of the horizontal and the vertical motion component of every frame
-// (paper §V: the environment vector E_t holds Var_x(F_mv) and Var_y(F_mv);
+// (paper §IV-C, Eq. 1: the environment vector E_t holds Var_x(F_mv) and Var_y(F_mv);
 // Table IV: the motion variance is the feature that reveals dynamic objects).
 //
 // The motion planes are streamed once (8 bytes per pixel, HBM bound). Each

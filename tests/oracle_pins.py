@@ -13,6 +13,11 @@ raises ``AssertionError`` when it disagrees with:
 * a hand-worked example (``tests/golden/hand_2x3.json``),
 * the scene generator's own motion (an integer pan).
 
+An implementation with ``O.exact`` true takes the displacement ``s*u``
+exactly (the plain definition); otherwise ``s*u`` is rounded once to float32.
+The pins that depend on the displacement compute it the same way, from the
+phase and the motion alone.
+
 The same pins run on planted mistakes in ``test_oracle_mutants.py`` to show
 that each plausible mistake fails at least one of them.
 """
@@ -81,13 +86,22 @@ def pin_constant(O):
     assert np.abs(out - exp).max() <= 1e-15
 
 
+def _exact(O) -> bool:
+    return bool(getattr(O, "exact", False))
+
+
+def _disp(O, s, comp):
+    """The displacement s*u in the mode of ``O``: the float64 product of the
+    float32 phase and motion (exact), or that product rounded to float32."""
+    prod = np.float64(np.float32(s)) * np.asarray(comp, np.float32).astype(np.float64)
+    return prod if _exact(O) else prod.astype(np.float32).astype(np.float64)
+
+
 def _sample_points(O, mv, s, h, w):
-    """Exact float64 sample coordinates implied by the float32 displacement."""
+    """Float64 sample coordinates x - d, y - d of the displacement of ``O``'s mode
+    (exact here: x and d are below 2^24 with at most 26 significant bits)."""
     ys, xs = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
-    def disp(comp):
-        prod = np.float64(np.float32(s)) * comp.astype(np.float64)
-        return prod.astype(np.float32).astype(np.float64)
-    return xs - disp(mv[0]), ys - disp(mv[1])
+    return xs - _disp(O, s, mv[0]), ys - _disp(O, s, mv[1])
 
 
 def pin_closed_forms(O):
@@ -115,23 +129,38 @@ def pin_closed_forms(O):
         assert (out[0, 0][:, ~ok] == 0).all()
 
 
-def _brute_valid(d32x, d32y, x, y, h, w):
+def _brute_valid(dx: Fraction, dy: Fraction, x, y, h, w):
     """Exact rational test: every tap with non-zero weight lies in the frame."""
-    sx = Fraction(x) - Fraction(float(d32x))
-    sy = Fraction(y) - Fraction(float(d32y))
+    sx = Fraction(x) - dx
+    sy = Fraction(y) - dy
     cols = {math.floor(sx), math.ceil(sx)}
     rows = {math.floor(sy), math.ceil(sy)}
     return all(0 <= c < w for c in cols) and all(0 <= r < h for r in rows)
 
 
+def _disp_fraction(O, s, u):
+    """The displacement as an exact rational (None when it is not finite)."""
+    if _exact(O):
+        if not np.isfinite(u):
+            return None
+        return Fraction(float(np.float32(s))) * Fraction(float(u))
+    d = np.float32(np.float64(np.float32(s)) * np.float64(u))
+    return Fraction(float(d)) if np.isfinite(d) else None
+
+
 def pin_mask_bruteforce(O):
     """Masks on tiny frames equal exact brute force, including at the exact bounds
-    and one float32 ulp either side; constant motion gives the closed-form count."""
+    and one float32 ulp either side, and at motions whose product with the phase
+    3/4 lies within an ulp of a bound (where the exact and the float32-rounded
+    displacement can fall on different sides of it); constant motion gives the
+    closed-form count."""
     for h, w in [(1, 1), (1, 3), (2, 2), (3, 5), (5, 3), (8, 8)]:
         vals = []
         for b in range(-w - 1, w + 2):
             f = np.float32(b)
             vals += [f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))]
+            g = np.float32(b / 0.75)
+            vals += [g, np.nextafter(g, np.float32(np.inf)), np.nextafter(g, np.float32(-np.inf))]
         vals += [np.float32(0.5), np.float32(-0.25), np.float32(np.nan), np.float32(np.inf),
                  np.float32(1e-40), np.float32(-1e-40), np.float32(-0.0)]
         vals = np.array(vals, dtype=np.float32)
@@ -141,9 +170,9 @@ def pin_mask_bruteforce(O):
             _, mask, cnt = O.forward(np.ones((1, 1, h, w)), mv, [s])
             for y in range(h):
                 for x in range(w):
-                    dx = np.float32(np.float64(np.float32(s)) * np.float64(mv[0, 0, y, x]))
-                    dy = np.float32(np.float64(np.float32(s)) * np.float64(mv[0, 1, y, x]))
-                    exp = (bool(np.isfinite(dx) and np.isfinite(dy))
+                    dx = _disp_fraction(O, s, mv[0, 0, y, x])
+                    dy = _disp_fraction(O, s, mv[0, 1, y, x])
+                    exp = (dx is not None and dy is not None
                            and _brute_valid(dx, dy, x, y, h, w))
                     assert bool(mask[0, 0, y, x]) == exp, (h, w, s, x, y, dx, dy)
             assert cnt[0, 0] == h * w - int(mask.sum())

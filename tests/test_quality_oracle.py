@@ -90,8 +90,46 @@ def pin_ssim_brute_force(Q):
     assert abs(Q.ssim(x[None], y[None]) - ref.mean()) <= 1e-12
 
 
+def pin_ssim_checkerboard_closed_form(Q):
+    """A 1-px checkerboard chi against a negatively correlated copy.
+
+    x = a + dx * chi and y = p - dy * chi. Under the separable window the
+    weighted mean of chi at a position is m = e^2 + o^2 or 2 e o (by the
+    parity of the position), where e and o are the sums of the normalised
+    1-D Gaussian taps at even and at odd offsets; chi^2 = chi gives its
+    weighted variance m (1 - m). Hence mu_x = a + dx m, mu_y = p - dy m,
+    sigma_x^2 = dx^2 m (1 - m), sigma_y^2 = dy^2 m (1 - m) and the covariance
+    -dx dy m (1 - m), which is negative: this pins the structure term's sign
+    and its factor 2, which SSIM(x, x) = 1 and symmetry cannot."""
+    one = [math.exp(-((k - 5) ** 2) / (2 * 1.5 ** 2)) for k in range(11)]
+    tot = math.fsum(one)
+    e = math.fsum(one[k] for k in range(0, 11, 2)) / tot
+    o = math.fsum(one[k] for k in range(1, 11, 2)) / tot
+    h, w = 17, 22
+    chi = (np.indices((h, w)).sum(axis=0) % 2).astype(np.float64)
+    for a, dx, p, dy, peak in ((0.0, 1.0, 1.0, 1.0, 1.0), (0.2, 0.5, 0.9, 0.3, 1.0),
+                               (0.1, 0.05, 0.6, 0.4, 1.0), (30.0, 180.0, 250.0, 200.0, 255.0)):
+        x = a + dx * chi
+        y = p - dy * chi
+        expect = np.empty((h - 10, w - 10))
+        for i in range(h - 10):
+            for j in range(w - 10):
+                # chi = 1 where the offset parity differs from the corner's
+                m = 2 * e * o if (i + j) % 2 == 0 else e * e + o * o
+                mx, my = a + dx * m, p - dy * m
+                vx, vy = dx * dx * m * (1 - m), dy * dy * m * (1 - m)
+                cxy = -dx * dy * m * (1 - m)
+                c1, c2 = (0.01 * peak) ** 2, (0.03 * peak) ** 2
+                expect[i, j] = ((2 * mx * my + c1) * (2 * cxy + c2)) / (
+                    (mx * mx + my * my + c1) * (vx + vy + c2))
+        got = Q.ssim_map(x, y, peak)
+        assert np.abs(got - expect).max() <= 1e-10, (a, dx, p, dy, float(np.abs(got - expect).max()))
+        assert abs(Q.ssim(x[None], y[None], peak) - expect.mean()) <= 1e-10
+        assert expect.max() < 0.5  # far from 1: the structure term is active
+
+
 ALL = [pin_psnr_closed_form, pin_ssim_identity_and_constants, pin_ssim_symmetry_and_window,
-       pin_ssim_brute_force]
+       pin_ssim_brute_force, pin_ssim_checkerboard_closed_form]
 
 
 @pytest.mark.parametrize("pin", ALL, ids=[p.__name__ for p in ALL])
@@ -128,7 +166,8 @@ def _psnr_255(a, b, peak=1.0):
     return math.inf if m == 0 else 10 * math.log10(255.0 ** 2 / m)
 
 
-def _ssim_map_with(window=None, pad=False, k1=0.01, k2=0.03, cov=True):
+def _ssim_map_with(window=None, pad=False, k1=0.01, k2=0.03, cov=True, cov_sign=1.0,
+                   cov_factor=2.0):
     from scipy.signal import fftconvolve
 
     def f(x, y, peak=1.0):
@@ -141,8 +180,9 @@ def _ssim_map_with(window=None, pad=False, k1=0.01, k2=0.03, cov=True):
         c1, c2 = (k1 * peak) ** 2, (k2 * peak) ** 2
         mx, my = ws(x), ws(y)
         sxx, syy = ws(x * x) - mx * mx, ws(y * y) - my * my
-        sxy = ws(x * y) - mx * my if cov else np.zeros_like(mx)
-        return ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+        sxy = cov_sign * (ws(x * y) - mx * my) if cov else np.zeros_like(mx)
+        return (((2 * mx * my + c1) * (cov_factor * sxy + c2))
+                / ((mx * mx + my * my + c1) * (sxx + syy + c2)))
     return f
 
 
@@ -166,7 +206,17 @@ MUTANTS = {
     "zero_padding": _mutant_ssim(pad=True),
     "swapped_constants": _mutant_ssim(k1=0.03, k2=0.01),
     "no_covariance": _mutant_ssim(cov=False),
+    "covariance_sign": _mutant_ssim(cov_sign=-1.0),
+    "covariance_without_factor_2": _mutant_ssim(cov_factor=1.0),
 }
+
+
+def test_checkerboard_pin_alone_catches_the_covariance_mutants():
+    """The closed form with negative covariance is what pins the structure term:
+    it rejects a flipped sign and a dropped factor 2 on its own."""
+    for name in ("covariance_sign", "covariance_without_factor_2", "no_covariance"):
+        with pytest.raises(AssertionError):
+            pin_ssim_checkerboard_closed_form(MUTANTS[name])
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -1,6 +1,6 @@
 """Pins of the scene-statistics oracle (CPU only).
 
-The per-frame motion mean and population variance (paper §V, E_t) are
+The per-frame motion mean and population variance (paper §IV-C, Eq. 1, E_t) are
 checked against facts fixed outside the oracle: exact rational arithmetic on
 small fields, closed forms (constant, two-valued and ramp fields), the
 invariances of a variance (shift, scale, permutation), and NumPy's own
