@@ -226,6 +226,48 @@ size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w);
 exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
                             void *workspace, size_t workspace_bytes, void *stream);
 
+
+/* ------------------------------------------------------------------------
+ * EMD features of the state.
+ *
+ * Paper §III-D (State Representation) and Table IV: the change of the world
+ * normal and world position buffers from F_t-1 to F_t is measured with the
+ * Earth Mover's Distance (EMD_{W_N}, EMD_{W_P}, entries of E_t in §IV-C,
+ * Eq. 1). The paper names the metric, not how a buffer becomes a
+ * distribution; here each channel's values over the frame form a histogram
+ * of `bins` uniform bins on [lo, hi], and the EMD of the two unit-mass
+ * histograms with ground distance |i - j| * width (width = (hi - lo) / bins)
+ * is, in one dimension, sum_i |CA_i - CB_i| / (H*W) * width over the
+ * cumulative counts CA, CB. A buffer's feature is the sum over its channels.
+ * ------------------------------------------------------------------------ */
+
+#define EXW_EMD_MAX_BINS 4096
+
+/* Bytes of device workspace exw_buffer_emd needs: 2 * bins 32-bit counters
+ * per frame and channel. Returns 0 for an empty batch or bins out of range. */
+size_t exw_buffer_emd_workspace_bytes(int32_t n, int32_t c, int32_t bins);
+
+/*
+ * Per-frame, per-channel EMD between two buffers:
+ *   emd[n][c] = EMD between the values of cur[n, c] and of prev[n, c].
+ *   cur, prev: [N, C, H, W] in `dtype` (the buffer of F_t and of F_t-1),
+ *              device, aligned to the element size.
+ *   lo < hi:   finite float64 range of the bins; a value v falls in bin
+ *              floor((v - lo) * (bins / (hi - lo))), computed in float64
+ *              and clamped to [0, bins - 1] (values outside [lo, hi] join
+ *              the end bins; NaN joins bin 0).
+ *   bins:      1 .. EXW_EMD_MAX_BINS.
+ *   emd:       [N, C] float64, device, 8-byte aligned; overwritten.
+ *   workspace: device scratch of at least exw_buffer_emd_workspace_bytes()
+ *              bytes, 256-byte aligned.
+ * Counts are integers, so results do not depend on the order of the
+ * atomics that build them. N = 0 does nothing; N > 0 with H = 0 or W = 0 is
+ * EXW_ERROR_INVALID_VALUE (an empty frame has no distribution).
+ */
+exw_status exw_buffer_emd(const void *cur, const void *prev, exw_dtype dtype, int32_t n,
+                          int32_t c, int32_t h, int32_t w, double lo, double hi, int32_t bins,
+                          double *emd, void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Frame quality.
  *
@@ -336,6 +378,24 @@ exw_status exw_threshold_policy(const double *motion_stats, const double *invali
 exw_status exw_warp_chain(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                           int32_t w, const float *mv, float phase, int32_t steps, void *out,
                           uint8_t *mask, uint32_t *invalid_count, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement: plain HBM streams.
+ *
+ * Not part of the method: the bandwidth ceiling the warp kernels are
+ * measured against (a copy, a read-only and a write-only sweep of device
+ * memory, 16 bytes per lane, one pass). The warp's algorithmic bytes per
+ * second are reported as a fraction of the vendor peak and of these.
+ *   bytes: a multiple of 16; pointers 16-byte aligned device memory.
+ *   exw_stream_copy: dst[0, bytes) = src[0, bytes); the ranges may not overlap.
+ *   exw_stream_read: reads src[0, bytes); `sink` (4 bytes of device memory,
+ *                    4-byte aligned) is never written but must be valid.
+ *   exw_stream_write: writes zeros to dst[0, bytes).
+ * Same conventions as the warp calls (stream, validation, no allocation).
+ * ------------------------------------------------------------------------ */
+exw_status exw_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+exw_status exw_stream_read(const void *src, size_t bytes, float *sink, void *stream);
+exw_status exw_stream_write(void *dst, size_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

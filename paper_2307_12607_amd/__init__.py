@@ -38,9 +38,14 @@ from .binding import (  # noqa: F401
     exw_warp_chain,
     exw_motion_stats,
     exw_motion_stats_workspace_bytes,
+    exw_buffer_emd,
+    exw_buffer_emd_workspace_bytes,
     exw_warp_forward,
     exw_warp_forward_batched,
     exw_warp_forward_batched_record,
+    exw_stream_copy,
+    exw_stream_read,
+    exw_stream_write,
 )
 
 # Fail at import, not at first use, when the native library is absent.
@@ -149,6 +154,22 @@ def motion_stats(mv: torch.Tensor) -> torch.Tensor:
     return stats
 
 
+def buffer_emd(cur: torch.Tensor, prev: torch.Tensor, lo: float, hi: float,
+               bins: int = 256) -> torch.Tensor:
+    """Per-frame, per-channel EMD between buffers ``cur`` (of F_t) and ``prev``
+    (of F_t-1), both [N,C,H,W] of one dtype, over ``bins`` histogram bins on
+    [lo, hi]: a float64 [N,C] device tensor. The state feature of a buffer
+    (EMD_{W_N}, EMD_{W_P}) is its sum over channels."""
+    cur = cur.contiguous()
+    prev = prev.contiguous()
+    n, c = cur.shape[:2]
+    emd = torch.empty((n, c), dtype=torch.float64, device=cur.device)
+    nbytes = exw_buffer_emd_workspace_bytes(n, c, bins)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=cur.device)
+    exw_buffer_emd(cur, prev, lo, hi, bins, emd, ws)
+    return emd
+
+
 def frame_quality(pred: torch.Tensor, truth: torch.Tensor, peak: float = 1.0) -> torch.Tensor:
     """Per-frame ``(MSE, PSNR, SSIM)`` of ``pred`` against ``truth``, both
     [..., C, H, W] of one dtype, as a float64 [..., 3] device tensor."""
@@ -234,4 +255,6 @@ __all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differenti
            "exw_motion_stats",
            "exw_motion_stats_workspace_bytes", "exw_frame_quality",
            "exw_frame_quality_workspace_bytes", "exw_warp_chain", "exw_decision_plan",
-           "exw_threshold_policy"]
+           "exw_threshold_policy", "exw_stream_copy", "exw_stream_read", "exw_stream_write",
+           "exw_buffer_emd", "exw_buffer_emd_workspace_bytes",
+           "buffer_emd"]

@@ -17,6 +17,7 @@ EXW_SUCCESS, EXW_ERROR_INVALID_VALUE, EXW_ERROR_UNSUPPORTED, EXW_ERROR_LAUNCH = 
 EXW_ABI_VERSION = 1
 EXW_MAX_PHASES = 4
 EXW_MAX_CHANNELS = 64
+EXW_EMD_MAX_BINS = 4096
 
 # name -> (restype, argtypes), in the order of include/exwarp.h
 _i32 = ctypes.c_int32
@@ -48,6 +49,12 @@ SIGNATURES = {
                                       _p, _p, _p]),
     "exw_frame_quality": (ctypes.c_int, [_p, _p, ctypes.c_int, _i32, _i32, _i32, _i32,
                                          ctypes.c_double, _p, _p, _sz, _p]),
+    "exw_buffer_emd_workspace_bytes": (_sz, [_i32, _i32, _i32]),
+    "exw_buffer_emd": (ctypes.c_int, [_p, _p, ctypes.c_int, _i32, _i32, _i32, _i32,
+                                      ctypes.c_double, ctypes.c_double, _i32, _p, _p, _sz, _p]),
+    "exw_stream_copy": (ctypes.c_int, [_p, _p, _sz, _p]),
+    "exw_stream_read": (ctypes.c_int, [_p, _sz, _p, _p]),
+    "exw_stream_write": (ctypes.c_int, [_p, _sz, _p]),
 }
 
 

@@ -217,6 +217,33 @@ def exw_motion_stats(mv: torch.Tensor, stats: torch.Tensor,
     check(st, "exw_motion_stats")
 
 
+def exw_buffer_emd_workspace_bytes(n: int, c: int, bins: int) -> int:
+    return int(lib().exw_buffer_emd_workspace_bytes(n, c, bins))
+
+
+def exw_buffer_emd(cur: torch.Tensor, prev: torch.Tensor, lo: float, hi: float, bins: int,
+                   emd: torch.Tensor, workspace: Optional[torch.Tensor] = None,
+                   stream=None) -> None:
+    """cur, prev [N,C,H,W] (one dtype) -> emd [N,C] f64: per-channel EMD between
+    the value histograms (``bins`` bins on [lo, hi]). ``workspace``: a byte
+    tensor of at least ``exw_buffer_emd_workspace_bytes`` bytes."""
+    dev = cur.device
+    _dev(cur, "cur", dev)
+    if cur.dim() != 4:
+        raise ValueError(f"cur has shape {tuple(cur.shape)}, expected [N, C, H, W]")
+    n, c, h, w = cur.shape
+    _expect(prev, "prev", (n, c, h, w), cur.dtype, dev)
+    _expect(emd, "emd", (n, c), torch.float64, dev)
+    ws_bytes = 0
+    if workspace is not None:
+        _dev(workspace, "workspace", dev)
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib().exw_buffer_emd(_ptr(cur), _ptr(prev), exw_dtype(cur.dtype), n, c, h, w,
+                              ctypes.c_double(lo), ctypes.c_double(hi), bins, _ptr(emd),
+                              _ptr(workspace), ws_bytes, _stream(dev, stream))
+    check(st, "exw_buffer_emd")
+
+
 def exw_frame_quality_workspace_bytes(b: int, c: int, h: int, w: int) -> int:
     return int(lib().exw_frame_quality_workspace_bytes(b, c, h, w))
 
@@ -290,3 +317,36 @@ __all__ = ["ExwError", "exw_dtype", "exw_warp_forward_batched", "exw_warp_forwar
            "exw_motion_stats_workspace_bytes", "exw_motion_stats",
            "exw_frame_quality_workspace_bytes", "exw_frame_quality", "exw_warp_chain",
            "exw_decision_plan", "exw_threshold_policy", "_capi"]
+
+
+def _bytes_of(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def exw_stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst <- src (same byte size, contiguous device tensors): the plain HBM copy
+    the warp kernels are measured against."""
+    dev = src.device
+    _dev(src, "src", dev)
+    _dev(dst, "dst", dev)
+    if _bytes_of(src) != _bytes_of(dst):
+        raise ValueError("src and dst differ in size")
+    check(lib().exw_stream_copy(_ptr(src), _ptr(dst), _bytes_of(src), _stream(dev, stream)),
+          "exw_stream_copy")
+
+
+def exw_stream_read(src: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """Reads every byte of src (sink: a float32 device tensor, never written)."""
+    dev = src.device
+    _dev(src, "src", dev)
+    _expect(sink, "sink", tuple(sink.shape), torch.float32, dev)
+    check(lib().exw_stream_read(_ptr(src), _bytes_of(src), _ptr(sink), _stream(dev, stream)),
+          "exw_stream_read")
+
+
+def exw_stream_write(dst: torch.Tensor, stream=None) -> None:
+    """Writes zeros over every byte of dst."""
+    dev = dst.device
+    _dev(dst, "dst", dev)
+    check(lib().exw_stream_write(_ptr(dst), _bytes_of(dst), _stream(dev, stream)),
+          "exw_stream_write")

@@ -261,6 +261,9 @@ exw_status backward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c,
                     "warp backward launch");
 }
 
+exw_status motion_stats_impl(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
 }  // namespace
 
 extern "C" {
@@ -344,6 +347,15 @@ size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w) {
 
 exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
                             void *workspace, size_t workspace_bytes, void *stream) {
+    return motion_stats_impl(mv, n, h, w, stats, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+exw_status motion_stats_impl(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
+                             void *workspace, size_t workspace_bytes, void *stream) {
     if (n < 0 || h < 0 || w < 0)
         return fail(EXW_ERROR_INVALID_VALUE, "negative size (n=%d, h=%d, w=%d)", n, h, w);
     if (n > 0 && (h == 0 || w == 0))
@@ -359,8 +371,8 @@ exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, do
     if (n >= (1 << 21)) return fail(EXW_ERROR_UNSUPPORTED, "frame count %d >= 2^21", n);
     EXW_TRY(check_ptr("mv", mv, 4, true));
     EXW_TRY(check_ptr("stats", stats, 8, true));
-    EXW_TRY(check_ptr("workspace", workspace, 256, true));
     const size_t ws_need = exw::motion_stats_workspace_bytes(n, h, w);
+    EXW_TRY(check_ptr("workspace", workspace, 256, true));
     if (workspace_bytes < ws_need)
         return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
                     workspace_bytes, ws_need);
@@ -372,6 +384,10 @@ exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, do
                                              static_cast<hipStream_t>(stream)),
                     "motion statistics launch");
 }
+
+}  // namespace
+
+extern "C" {
 
 size_t exw_frame_quality_workspace_bytes(int32_t b, int32_t c, int32_t h, int32_t w) {
     if (b <= 0 || c <= 0 || h < 11 || w < 11) return 0;
@@ -421,6 +437,59 @@ exw_status exw_frame_quality(const void *pred, const void *truth, exw_dtype dtyp
                     "frame quality launch");
 }
 
+size_t exw_buffer_emd_workspace_bytes(int32_t n, int32_t c, int32_t bins) {
+    if (n <= 0 || c <= 0 || bins < 1 || bins > EXW_EMD_MAX_BINS) return 0;
+    return exw::buffer_emd_workspace_bytes(n, c, bins);
+}
+
+exw_status exw_buffer_emd(const void *cur, const void *prev, exw_dtype dtype, int32_t n,
+                          int32_t c, int32_t h, int32_t w, double lo, double hi, int32_t bins,
+                          double *emd, void *workspace, size_t workspace_bytes, void *stream) {
+    const size_t esize = dtype_size(dtype);
+    if (esize == 0) return fail(EXW_ERROR_INVALID_VALUE, "unknown dtype %d", int(dtype));
+    if (n < 0 || h < 0 || w < 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "negative size (n=%d, h=%d, w=%d)", n, h, w);
+    if (c < 1) return fail(EXW_ERROR_INVALID_VALUE, "channel count %d < 1", c);
+    if (c > EXW_MAX_CHANNELS)
+        return fail(EXW_ERROR_UNSUPPORTED, "channel count %d > %d", c, EXW_MAX_CHANNELS);
+    if (!(std::isfinite(lo) && std::isfinite(hi) && lo < hi))
+        return fail(EXW_ERROR_INVALID_VALUE, "the bin range needs finite lo < hi");
+    if (bins < 1 || bins > EXW_EMD_MAX_BINS)
+        return fail(EXW_ERROR_INVALID_VALUE, "bins %d outside 1..%d", bins, EXW_EMD_MAX_BINS);
+    if (!std::isfinite(double(bins) / (hi - lo)))
+        return fail(EXW_ERROR_INVALID_VALUE, "bin range too narrow for %d bins", bins);
+    if (n > 0 && (h == 0 || w == 0))
+        return fail(EXW_ERROR_INVALID_VALUE, "empty frames have no distribution (h=%d, w=%d)",
+                    h, w);
+    if (n == 0) return succeed();
+    const uint64_t hw = uint64_t(h) * uint64_t(w);
+    if (hw > (uint64_t(1) << 30))
+        return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu > 2^30", (unsigned long long)hw);
+    const uint64_t elems = uint64_t(n) * uint64_t(c) * hw;
+    if (elems > kMaxElems)
+        return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu elements)",
+                    (unsigned long long)elems);
+    // at most 128 workgroups per plane in a 1-D grid
+    if (uint64_t(n) * uint64_t(c) * 128u >= (uint64_t(1) << 31))
+        return fail(EXW_ERROR_UNSUPPORTED, "too many planes (%llu)",
+                    (unsigned long long)(uint64_t(n) * uint64_t(c)));
+    EXW_TRY(check_ptr("cur", cur, esize, true));
+    EXW_TRY(check_ptr("prev", prev, esize, true));
+    EXW_TRY(check_ptr("emd", emd, 8, true));
+    EXW_TRY(check_ptr("workspace", workspace, 256, true));
+    const size_t ws_need = exw::buffer_emd_workspace_bytes(n, c, bins);
+    if (workspace_bytes < ws_need)
+        return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
+                    workspace_bytes, ws_need);
+    const Span ins[] = {span("cur", cur, elems * esize), span("prev", prev, elems * esize)};
+    const Span outs[] = {span("emd", emd, uint64_t(n) * uint64_t(c) * 8u),
+                         span("workspace", workspace, ws_need)};
+    EXW_TRY(check_disjoint(outs, 2, ins, 2));
+    return launched(exw::launch_buffer_emd(dtype, cur, prev, n, c, h, w, lo, hi, bins, emd,
+                                           workspace, static_cast<hipStream_t>(stream)),
+                    "buffer EMD launch");
+}
+
 exw_status exw_warp_chain(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                           int32_t w, const float *mv, float phase, int32_t steps, void *out,
                           uint8_t *mask, uint32_t *invalid_count, void *stream) {
@@ -459,6 +528,40 @@ exw_status exw_warp_chain(const void *src, exw_dtype dtype, int32_t n, int32_t c
         if (e != hipSuccess) return launched(e, "chained warp launch");
     }
     return succeed();
+}
+
+namespace {
+
+exw_status stream_impl(int kind, const void *src, void *dst, size_t bytes, float *sink,
+                       void *stream) {
+    if (bytes % 16 != 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "bytes %zu is not a multiple of 16", bytes);
+    if (bytes == 0) return succeed();
+    if (kind != 2) EXW_TRY(check_ptr("src", src, 16, true));
+    if (kind != 1) EXW_TRY(check_ptr("dst", dst, 16, true));
+    if (kind == 1) EXW_TRY(check_ptr("sink", sink, 4, true));
+    if (kind == 0) {
+        const Span ins[] = {span("src", src, bytes)};
+        const Span outs[] = {span("dst", dst, bytes)};
+        EXW_TRY(check_disjoint(outs, 1, ins, 1));
+    }
+    return launched(exw::launch_stream(kind, src, dst, static_cast<int64_t>(bytes), sink,
+                                       static_cast<hipStream_t>(stream)),
+                    "stream launch");
+}
+
+}  // namespace
+
+exw_status exw_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    return stream_impl(0, src, dst, bytes, nullptr, stream);
+}
+
+exw_status exw_stream_read(const void *src, size_t bytes, float *sink, void *stream) {
+    return stream_impl(1, src, nullptr, bytes, sink, stream);
+}
+
+exw_status exw_stream_write(void *dst, size_t bytes, void *stream) {
+    return stream_impl(2, nullptr, dst, bytes, nullptr, stream);
 }
 
 }  // extern "C"

@@ -75,4 +75,16 @@ hipError_t launch_quality(int dtype, const void *pred, const void *truth, int b,
                           int w, double peak, double *quality, void *workspace,
                           hipStream_t stream);
 
+// Per-frame, per-channel EMD between two buffers [N, C, H, W] (histograms of
+// `bins` bins on [lo, hi]); emd[n][c] in float64.
+size_t buffer_emd_workspace_bytes(int n, int c, int bins);
+hipError_t launch_buffer_emd(int dtype, const void *cur, const void *prev, int n, int c, int h,
+                             int w, double lo, double hi, int bins, double *emd, void *workspace,
+                             hipStream_t stream);
+
+// Plain HBM streams (kind 0 = copy src -> dst, 1 = read src, 2 = write dst),
+// bytes a multiple of 16, 16-byte aligned pointers.
+hipError_t launch_stream(int kind, const void *src, void *dst, int64_t bytes, float *sink,
+                         hipStream_t stream);
+
 }  // namespace exw

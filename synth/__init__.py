@@ -13,4 +13,6 @@ from .scenes import (  # noqa: F401
     pan_rect_sequence,
     random_field_frames,
     quantize,
+    upstream_gradient,
+    world_position,
 )

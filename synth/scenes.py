@@ -290,3 +290,45 @@ def quantize(x: np.ndarray, dtype: str) -> np.ndarray:
         t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))
         return t.to(torch.bfloat16).to(torch.float32).numpy()
     raise ValueError(f"unknown storage dtype {dtype!r}")
+
+
+def upstream_gradient(seed: int, shape) -> np.ndarray:
+    """A stand-in for dL/d out: i.i.d. uniform values in [-1, 1), float32.
+
+    Drawn per frame from its own seed, so that any frame of a batch can be
+    drawn again on its own (uniform rather than normal: four times cheaper to
+    draw at the size of a 4K batch).
+    """
+    rng = np.random.default_rng(seed)
+    g = rng.random(size=tuple(shape), dtype=np.float32)
+    g *= 2.0
+    g -= 1.0
+    return g
+
+
+# World position of the G-buffer scene: a pinhole camera of focal length W px
+# looks down +z; a pixel's view depth is near + depth * (far - near) (depth =
+# G-buffer channel 3); the camera moves with the pan, so that a point of the
+# background keeps its world position from frame to frame.
+WORLD_NEAR, WORLD_FAR = 1.0, 100.0
+
+
+def world_position(depth: np.ndarray, pan, frame0: int = 0) -> np.ndarray:
+    """World-position buffer [N, 3, H, W] float32 (x, y, z) of frames
+    frame0 .. frame0 + N - 1 from their depth channel [N, H, W] and the
+    sequence's camera pan (px per frame)."""
+    depth = np.asarray(depth, dtype=np.float64)
+    n, h, w = depth.shape
+    f = float(w)
+    z = WORLD_NEAR + depth * (WORLD_FAR - WORLD_NEAR)
+    z_bg = WORLD_NEAR + 0.95 * (WORLD_FAR - WORLD_NEAR)  # the background's depth
+    xs = np.arange(w, dtype=np.float64)[None, None, :] - w / 2.0
+    ys = np.arange(h, dtype=np.float64)[None, :, None] - h / 2.0
+    t = (frame0 + np.arange(n, dtype=np.float64))[:, None, None]
+    cam_x = -t * float(pan[0]) * z_bg / f
+    cam_y = -t * float(pan[1]) * z_bg / f
+    out = np.empty((n, 3, h, w), dtype=np.float32)
+    out[:, 0] = xs * z / f + cam_x
+    out[:, 1] = ys * z / f + cam_y
+    out[:, 2] = z
+    return out

@@ -64,3 +64,53 @@ def assert_close_kernel(gpu: np.ndarray, ref: np.ndarray, dtype: str, what: str)
     assert not bad.any(), (f"{what}: {int(bad.sum())} elements beyond half an ulp; worst "
                            f"{float(err.max())}")
     return float(err.max()) if err.size else 0.0
+
+
+def rounding_band(mv: np.ndarray, phase: float, h: int, w: int) -> np.ndarray:
+    """Pixels [.., H, W] where the float32 rounding of d = s*u (or s*v) can move
+    the validity decision: an integer bound of the box test (x, x - (W-1); y,
+    y - (H-1)) lies within half a float32 ulp of d of the exact d. Outside this
+    band the exact and the float32-rounded displacement decide alike."""
+    s32 = np.float32(phase)
+    mvf = np.asarray(mv, np.float32)
+    d32 = (s32 * mvf).astype(np.float32)
+    dex = np.float64(s32) * mvf.astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        half = np.abs(np.spacing(d32)).astype(np.float64) / 2
+        xs = np.arange(w, dtype=np.float64)[None, :]
+        ys = np.arange(h, dtype=np.float64)[:, None]
+        bx, by = dex[..., 0, :, :], dex[..., 1, :, :]
+        hx, hy = half[..., 0, :, :], half[..., 1, :, :]
+        return ((np.abs(bx - xs) <= hx) | (np.abs(bx - (xs - (w - 1))) <= hx)
+                | (np.abs(by - ys) <= hy) | (np.abs(by - (ys - (h - 1))) <= hy))
+
+
+def compare_with_exact(gpu_out: np.ndarray, gpu_mask: np.ndarray, ex_out: np.ndarray,
+                       ex_mask: np.ndarray, mv: np.ndarray, phases, dtype: str,
+                       what: str) -> dict:
+    """The GPU forward [N,K,C,H,W] against the oracle's exact mode (d = s*u in
+    float64): mask mismatches only inside the rounding band, counted; values
+    of pixels valid on both sides within 1e-5 (f32) or half an ulp of the
+    storage type plus 1e-5 (f16/bf16). Returns the counts and the worst error."""
+    n, k = gpu_mask.shape[:2]
+    h, w = gpu_mask.shape[-2:]
+    in_band = mismatches = 0
+    worst = 0.0
+    for j, s in enumerate(phases):
+        band = rounding_band(mv, s, h, w)  # [N, H, W]
+        diff = gpu_mask[:, j] != ex_mask[:, j]
+        assert not (diff & ~band).any(), (
+            f"{what}: {int((diff & ~band).sum())} mask mismatches outside the rounding band")
+        mismatches += int(diff.sum())
+        in_band += int(band.sum())
+        both = (gpu_mask[:, j] == 1) & (ex_mask[:, j] == 1)
+        err = np.abs(gpu_out[:, j] - ex_out[:, j]) * both[:, None]
+        if dtype == "f32":
+            bound = 1e-5
+        else:
+            bound = half_ulp(ex_out[:, j], dtype) + 1e-5
+        assert (err <= bound).all(), f"{what}: phase {s} value error {float(err.max())} vs exact"
+        worst = max(worst, float(err.max()) if err.size else 0.0)
+    print(f"[exact-mode] {what}: band pixels {in_band}, mask mismatches in band "
+          f"{mismatches}, max value error {worst:.3g}", flush=True)
+    return {"band_pixels": in_band, "band_mismatches": mismatches, "max_abs_vs_exact": worst}

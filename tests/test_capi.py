@@ -326,3 +326,59 @@ def test_product_path_never_touches_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"\boracle\b|warp_ref|synth", text), f
+
+
+@pytest.mark.parametrize("call,args,needle", [
+    ("exw_stream_copy", (FAKE, FAKE + (1 << 30), 100, None), "multiple of 16"),
+    ("exw_stream_copy", (None, FAKE, 64, None), "src is NULL"),
+    ("exw_stream_copy", (FAKE + 8, FAKE + (1 << 30), 64, None), "src is not 16-byte aligned"),
+    ("exw_stream_copy", (FAKE, FAKE + 32, 64, None), "overlaps"),
+    ("exw_stream_read", (FAKE, 64, None, None), "sink is NULL"),
+    ("exw_stream_read", (FAKE, 48, FAKE + 2, None), "sink is not 4-byte aligned"),
+    ("exw_stream_write", (FAKE + 4, 64, None), "dst is not 16-byte aligned"),
+])
+def test_stream_calls_reject(call, args, needle):
+    st = getattr(_capi.lib(), call)(*args)
+    assert st == _capi.EXW_ERROR_INVALID_VALUE
+    assert needle in _capi.last_error()
+
+
+def test_stream_calls_of_zero_bytes_are_no_ops():
+    for call, args in (("exw_stream_copy", (FAKE, FAKE, 0, None)),
+                       ("exw_stream_read", (FAKE, 0, FAKE, None)),
+                       ("exw_stream_write", (FAKE, 0, None))):
+        assert getattr(_capi.lib(), call)(*args) == _capi.EXW_SUCCESS
+
+
+def emd(cur=FAKE, prev=FAKE + (1 << 30), dtype=0, n=1, c=3, h=8, w=8, lo=-1.0, hi=1.0, bins=64,
+        out=FAKE + (2 << 30), ws=FAKE + (3 << 30), ws_bytes=1 << 20):
+    return _capi.lib().exw_buffer_emd(cur, prev, dtype, n, c, h, w, lo, hi, bins, out, ws,
+                                      ws_bytes, None)
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(dtype=7), 1, "unknown dtype"),
+    (dict(c=0), 1, "channel count"),
+    (dict(c=65), 2, "channel count"),
+    (dict(lo=1.0, hi=1.0), 1, "finite lo < hi"),
+    (dict(lo=float("nan")), 1, "finite lo < hi"),
+    (dict(hi=float("inf")), 1, "finite lo < hi"),
+    (dict(bins=0), 1, "bins 0"),
+    (dict(bins=4097), 1, "bins 4097"),
+    (dict(h=0), 1, "empty frames"),
+    (dict(cur=None), 1, "cur is NULL"),
+    (dict(prev=FAKE + 2), 1, "prev is not 4-byte aligned"),
+    (dict(ws_bytes=100), 1, "workspace has 100 bytes"),
+    (dict(out=FAKE + 64), 1, "emd overlaps input cur"),
+])
+def test_buffer_emd_rejects(kwargs, status, needle):
+    assert emd(**kwargs) == status
+    assert needle in _capi.last_error(), _capi.last_error()
+
+
+def test_buffer_emd_empty_batch_and_workspace_size():
+    assert emd(n=0) == _capi.EXW_SUCCESS
+    L = _capi.lib()
+    assert L.exw_buffer_emd_workspace_bytes(2, 3, 100) == 2 * 3 * 2 * 100 * 4
+    assert L.exw_buffer_emd_workspace_bytes(0, 3, 100) == 0
+    assert L.exw_buffer_emd_workspace_bytes(1, 3, 4097) == 0

@@ -7,8 +7,8 @@ import torch
 import paper_2307_12607_amd as exw
 from oracle import warp_oracle
 from synth import make_config
-from gpu_util import (E2E_TOL, announce, assert_close_kernel, need_gpu, stored, to_dev,
-                      to_host)
+from gpu_util import (E2E_TOL, announce, assert_close_kernel, compare_with_exact, need_gpu,
+                      rounding_band, stored, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +40,9 @@ def test_forward_matches_oracle(index):
         assert np.array_equal(mask, ref_mask), f"mask differs in {int((mask != ref_mask).sum())}"
         assert np.array_equal(cnt, ref_cnt)
         assert_close_kernel(out, ref, dtype, f"config {index} {dtype}")
+        ex, ex_mask, _ = warp_oracle.forward(src_q, d["mv"], phases, exact=True)
+        compare_with_exact(out, mask, ex, ex_mask, d["mv"], phases, dtype,
+                           f"config {index} {dtype}")
         # end to end: against the oracle on the float32 original frames
         ref32, _, _ = warp_oracle.forward(d["src"], d["mv"], phases)
         assert np.abs(out - ref32).max() <= E2E_TOL[dtype]
@@ -143,6 +146,9 @@ def test_edge_cases_shapes_and_channels():
             ref, ref_mask, ref_cnt = warp_oracle.forward(stored(src, dtype), mv, phases)
             assert np.array_equal(mask, ref_mask) and np.array_equal(cnt, ref_cnt)
             assert_close_kernel(out, ref, dtype, f"shape {(n, c, h, w, k)}")
+            ex, ex_mask, _ = warp_oracle.forward(stored(src, dtype), mv, phases, exact=True)
+            compare_with_exact(out, mask, ex, ex_mask, mv, phases, dtype,
+                               f"shape {(n, c, h, w, k)} {dtype}")
 
 
 def test_non_finite_huge_and_denormal_motion():
@@ -162,6 +168,35 @@ def test_non_finite_huge_and_denormal_motion():
         assert np.array_equal(cnt, ref_cnt)
         assert np.isfinite(out).all()
         assert np.abs(out - ref).max() <= 1e-5
+        ex, ex_mask, _ = warp_oracle.forward(src, mv, phases, exact=True)
+        compare_with_exact(out, mask, ex, ex_mask, mv, phases, "f32", f"specials {phases}")
+
+
+def test_three_quarter_phase_at_the_bounds_exact_vs_rounded():
+    """Motions whose product with the phase 3/4 lies within an ulp of a frame
+    bound: the GPU decides validity on the float32-rounded displacement, so
+    its masks equal the rounded-mode oracle bit for bit, and may differ from
+    the exact mode only inside the rounding band (where some of them do)."""
+    dev = need_gpu()
+    h, w = 9, 130
+    vals = []
+    for b in range(-w, w + 1):
+        g = np.float32(b / 0.75)
+        vals += [g, np.nextafter(g, np.float32(np.inf)), np.nextafter(g, np.float32(-np.inf))]
+    vals = np.array(vals, np.float32)
+    rng = np.random.default_rng(8)
+    mv = np.stack([rng.choice(vals, (h, w)), rng.uniform(-2, 2, (h, w)).astype(np.float32)])
+    mv = mv[None].astype(np.float32)
+    src = rng.random((1, 3, h, w), dtype=np.float32)
+    announce("3/4 phase at the bounds")
+    out, mask, cnt = run_forward(src, mv, [0.75], "f32", dev)
+    ref, ref_mask, ref_cnt = warp_oracle.forward(src, mv, [0.75])
+    assert np.array_equal(mask, ref_mask) and np.array_equal(cnt, ref_cnt)
+    assert np.abs(out - ref).max() <= 1e-5
+    ex, ex_mask, _ = warp_oracle.forward(src, mv, [0.75], exact=True)
+    st = compare_with_exact(out, mask, ex, ex_mask, mv, [0.75], "f32", "3/4 at the bounds")
+    assert st["band_pixels"] > 0
+    assert rounding_band(mv, 0.75, h, w).sum() == st["band_pixels"]
 
 
 def test_empty_batch_is_a_no_op():
