@@ -226,6 +226,25 @@ size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w);
 exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
                             void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * exw_motion_stats without a workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The workgroup
+ * partials live in a file-scope device array of EXW_NO_ALLOC_SCRATCH_BYTES
+ * bytes that the library holds on each GPU it runs on until the process
+ * ends (its address is looked up once per device, on the first call with
+ * that device current). Same arguments, results and errors as
+ * exw_motion_stats minus the workspace; a batch whose partials need more
+ * than EXW_NO_ALLOC_SCRATCH_BYTES (exw_motion_stats_workspace_bytes(n, h, w)
+ * > EXW_NO_ALLOC_SCRATCH_BYTES: e.g. more than 85 frames of 1080p) is
+ * EXW_ERROR_UNSUPPORTED. All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and give
+ * wrong statistics; calls ordered on one stream are safe (each call writes
+ * every partial it reads, so nothing needs clearing between calls).
+ */
+#define EXW_NO_ALLOC_SCRATCH_BYTES (1u << 20)
+exw_status exw_motion_stats_no_alloc(const float *mv, int32_t n, int32_t h, int32_t w,
+                                     double *stats, void *stream);
 
 /* ------------------------------------------------------------------------
  * EMD features of the state.

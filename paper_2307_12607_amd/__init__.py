@@ -38,6 +38,7 @@ from .binding import (  # noqa: F401
     exw_warp_chain,
     exw_motion_stats,
     exw_motion_stats_workspace_bytes,
+    exw_motion_stats_no_alloc,
     exw_buffer_emd,
     exw_buffer_emd_workspace_bytes,
     exw_warp_forward,
@@ -256,5 +257,5 @@ __all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differenti
            "exw_motion_stats_workspace_bytes", "exw_frame_quality",
            "exw_frame_quality_workspace_bytes", "exw_warp_chain", "exw_decision_plan",
            "exw_threshold_policy", "exw_stream_copy", "exw_stream_read", "exw_stream_write",
-           "exw_buffer_emd", "exw_buffer_emd_workspace_bytes",
+           "exw_motion_stats_no_alloc", "exw_buffer_emd", "exw_buffer_emd_workspace_bytes",
            "buffer_emd"]

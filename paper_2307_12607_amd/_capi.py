@@ -17,6 +17,7 @@ EXW_SUCCESS, EXW_ERROR_INVALID_VALUE, EXW_ERROR_UNSUPPORTED, EXW_ERROR_LAUNCH = 
 EXW_ABI_VERSION = 1
 EXW_MAX_PHASES = 4
 EXW_MAX_CHANNELS = 64
+EXW_NO_ALLOC_SCRATCH_BYTES = 1 << 20
 EXW_EMD_MAX_BINS = 4096
 
 # name -> (restype, argtypes), in the order of include/exwarp.h
@@ -42,6 +43,7 @@ SIGNATURES = {
                                                           _p, _p, _i32, _p, _p, _p, _p, _sz, _p]),
     "exw_motion_stats_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "exw_motion_stats": (ctypes.c_int, [_p, _i32, _i32, _i32, _p, _p, _sz, _p]),
+    "exw_motion_stats_no_alloc": (ctypes.c_int, [_p, _i32, _i32, _i32, _p, _p]),
     "exw_frame_quality_workspace_bytes": (_sz, [_i32, _i32, _i32, _i32]),
     "exw_decision_plan": (ctypes.c_int, [_i32, _i32, _i32, _p]),
     "exw_threshold_policy": (ctypes.c_int, [_p, _p, ctypes.c_double, ctypes.c_double, _p]),

@@ -217,6 +217,21 @@ def exw_motion_stats(mv: torch.Tensor, stats: torch.Tensor,
     check(st, "exw_motion_stats")
 
 
+def exw_motion_stats_no_alloc(mv: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
+    """exw_motion_stats with the library's static device scratch instead of a
+    workspace (no allocation; calls that overlap on one GPU race)."""
+    dev = mv.device
+    _dev(mv, "mv", dev)
+    if mv.dim() != 4 or mv.shape[1] != 2:
+        raise ValueError(f"mv has shape {tuple(mv.shape)}, expected [N, 2, H, W]")
+    if mv.dtype != torch.float32:
+        raise ValueError(f"mv has dtype {mv.dtype}, expected torch.float32")
+    n, _, h, w = mv.shape
+    _expect(stats, "stats", (n, 4), torch.float64, dev)
+    st = lib().exw_motion_stats_no_alloc(_ptr(mv), n, h, w, _ptr(stats), _stream(dev, stream))
+    check(st, "exw_motion_stats_no_alloc")
+
+
 def exw_buffer_emd_workspace_bytes(n: int, c: int, bins: int) -> int:
     return int(lib().exw_buffer_emd_workspace_bytes(n, c, bins))
 

@@ -262,7 +262,8 @@ exw_status backward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c,
 }
 
 exw_status motion_stats_impl(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
-                             void *workspace, size_t workspace_bytes, void *stream);
+                             void *workspace, size_t workspace_bytes, bool no_alloc,
+                             void *stream);
 
 }  // namespace
 
@@ -347,7 +348,12 @@ size_t exw_motion_stats_workspace_bytes(int32_t n, int32_t h, int32_t w) {
 
 exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
                             void *workspace, size_t workspace_bytes, void *stream) {
-    return motion_stats_impl(mv, n, h, w, stats, workspace, workspace_bytes, stream);
+    return motion_stats_impl(mv, n, h, w, stats, workspace, workspace_bytes, false, stream);
+}
+
+exw_status exw_motion_stats_no_alloc(const float *mv, int32_t n, int32_t h, int32_t w,
+                                     double *stats, void *stream) {
+    return motion_stats_impl(mv, n, h, w, stats, nullptr, 0, true, stream);
 }
 
 }  // extern "C"
@@ -355,7 +361,8 @@ exw_status exw_motion_stats(const float *mv, int32_t n, int32_t h, int32_t w, do
 namespace {
 
 exw_status motion_stats_impl(const float *mv, int32_t n, int32_t h, int32_t w, double *stats,
-                             void *workspace, size_t workspace_bytes, void *stream) {
+                             void *workspace, size_t workspace_bytes, bool no_alloc,
+                             void *stream) {
     if (n < 0 || h < 0 || w < 0)
         return fail(EXW_ERROR_INVALID_VALUE, "negative size (n=%d, h=%d, w=%d)", n, h, w);
     if (n > 0 && (h == 0 || w == 0))
@@ -372,14 +379,28 @@ exw_status motion_stats_impl(const float *mv, int32_t n, int32_t h, int32_t w, d
     EXW_TRY(check_ptr("mv", mv, 4, true));
     EXW_TRY(check_ptr("stats", stats, 8, true));
     const size_t ws_need = exw::motion_stats_workspace_bytes(n, h, w);
-    EXW_TRY(check_ptr("workspace", workspace, 256, true));
-    if (workspace_bytes < ws_need)
-        return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
-                    workspace_bytes, ws_need);
+    if (no_alloc) {
+        if (ws_need > exw::kNoAllocScratchBytes)
+            return fail(EXW_ERROR_UNSUPPORTED,
+                        "batch needs %zu bytes of partials, more than the %zu-byte static "
+                        "scratch of exw_motion_stats_no_alloc (use exw_motion_stats)",
+                        ws_need, exw::kNoAllocScratchBytes);
+    } else {
+        EXW_TRY(check_ptr("workspace", workspace, 256, true));
+        if (workspace_bytes < ws_need)
+            return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
+                        workspace_bytes, ws_need);
+    }
     const Span ins[] = {span("mv", mv, uint64_t(n) * 2u * hw * 4u)};
     const Span outs[] = {span("stats", stats, uint64_t(n) * 4u * 8u),
-                         span("workspace", workspace, ws_need)};
+                         span("workspace", no_alloc ? nullptr : workspace, ws_need)};
     EXW_TRY(check_disjoint(outs, 2, ins, 1));
+    if (no_alloc) {
+        void *scratch = nullptr;
+        const hipError_t e = exw::no_alloc_scratch(&scratch);
+        if (e != hipSuccess) return launched(e, "static scratch lookup");
+        workspace = scratch;
+    }
     return launched(exw::launch_motion_stats(mv, n, h, w, stats, workspace,
                                              static_cast<hipStream_t>(stream)),
                     "motion statistics launch");

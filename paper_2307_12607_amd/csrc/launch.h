@@ -68,6 +68,13 @@ size_t motion_stats_workspace_bytes(int n, int h, int w);
 hipError_t launch_motion_stats(const float *mv, int n, int h, int w, double *stats,
                                void *workspace, hipStream_t stream);
 
+// Size of the file-scope device scratch used by exw_motion_stats_no_alloc.
+constexpr size_t kNoAllocScratchBytes = EXW_NO_ALLOC_SCRATCH_BYTES;
+
+// That scratch's address on the current device (looked up once per device
+// with hipGetSymbolAddress, then cached).
+hipError_t no_alloc_scratch(void **ptr);
+
 // Per-frame (MSE, PSNR, SSIM) of pred vs truth, both [B, C, H, W] in the
 // storage dtype, H, W >= 11: quality[b][3] in float64.
 size_t quality_workspace_bytes(int b, int c, int h, int w);

@@ -11,6 +11,8 @@
 // (count, mean, M2) (Chan, Golub and LeVeque). Every fold is in a fixed order,
 // so results are reproducible, and no step forms E[x^2] - E[x]^2, which
 // cancels when the mean is large against the spread.
+#include <mutex>
+
 #include "launch.h"
 
 namespace exw {
@@ -137,7 +139,35 @@ int parts_for(int64_t hw) {
     return static_cast<int>(passes < kMaxParts ? passes : kMaxParts);
 }
 
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+// Scratch of the call that allocates nothing: the workgroup partials live in
+// a file-scope device array instead of a caller's workspace. Each device holds
+// its own copy at its own address; host code reaches it only through the
+// address hipGetSymbolAddress returns for that device (the array's name is a
+// host-side stand-in that no kernel may be given).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t no_alloc_scratch(void **ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        // once per device, with that device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t motion_stats_workspace_bytes(int n, int h, int w) {
     return sizeof(Moments) * 2 * static_cast<size_t>(n) *

@@ -350,6 +350,17 @@ def test_stream_calls_of_zero_bytes_are_no_ops():
         assert getattr(_capi.lib(), call)(*args) == _capi.EXW_SUCCESS
 
 
+def test_motion_stats_no_alloc_rejects_before_any_hip_call():
+    L = _capi.lib()
+    # beyond the static scratch: 200 x 1080p needs 200 x 256 partials of 48 bytes
+    assert L.exw_motion_stats_no_alloc(FAKE, 200, 1080, 1920, FAKE + (1 << 30), None) == \
+        _capi.EXW_ERROR_UNSUPPORTED
+    assert "static scratch" in _capi.last_error()
+    assert L.exw_motion_stats_no_alloc(None, 1, 8, 8, FAKE, None) == _capi.EXW_ERROR_INVALID_VALUE
+    assert L.exw_motion_stats_no_alloc(FAKE, 1, 0, 8, FAKE, None) == _capi.EXW_ERROR_INVALID_VALUE
+    assert L.exw_motion_stats_no_alloc(FAKE, 0, 8, 8, FAKE, None) == _capi.EXW_SUCCESS
+
+
 def emd(cur=FAKE, prev=FAKE + (1 << 30), dtype=0, n=1, c=3, h=8, w=8, lo=-1.0, hi=1.0, bins=64,
         out=FAKE + (2 << 30), ws=FAKE + (3 << 30), ws_bytes=1 << 20):
     return _capi.lib().exw_buffer_emd(cur, prev, dtype, n, c, h, w, lo, hi, bins, out, ws,
