@@ -65,6 +65,12 @@ CASES = [
     ("width 1", 1, 3, 17, 1, random_field(1, 17, 1, 2.0, 6), (0.5,), "f32"),
     ("C=5 (no footprint)", 1, 5, 20, 70, random_field(1, 20, 70, 2.0, 7), (1.0,), "f32"),
     ("narrow ragged", 3, 4, 6, 45, pan(3, 6, 45, -0.3, 0.7), (0.25, 0.5, 0.75), "f32"),
+    # 16-bit storage, several 128-pixel segments per row, a moving block, C = 12
+    ("wide pan f16", 2, 4, 21, 600, pan(2, 21, 600, 2.5, -3.0), (0.25, 0.5, 0.75), "f16"),
+    ("wide pan + block bf16 C=3", 1, 3, 30, 520,
+     pan(1, 30, 520, -1.3, 0.9, (8, 20, 200, 290, 6.5, -2.25)), (0.25, 0.5, 0.75, 1.0), "bf16"),
+    ("wide G-buffer C=12 K=2 f16", 1, 12, 11, 512, pan(1, 11, 512, 0.4, -1.6),
+     (0.5, 1.0), "f16"),
 ]
 
 

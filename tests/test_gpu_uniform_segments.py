@@ -100,3 +100,28 @@ def test_pan_with_moving_block_other_channel_counts(c):
     src = np.random.default_rng(9 + c).random((1, c, 64, 256)).astype(np.float32)
     mv = pan_field(1, 64, 256, 1.7, -0.6, rect=(20, 44, 70, 150, -5.5, 3.25))
     run_case(src, mv, (0.25, 0.5, 0.75) if c <= 4 else (1.0,), "f32", dev, f"block c={c}")
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("c,phases", [(1, (1.0,)), (3, (0.25, 0.5)), (4, (0.25, 0.5, 0.75)),
+                                       (4, (0.25, 0.5, 0.75, 1.0)), (12, (0.5, 1.0)),
+                                       (12, (1.0,))])
+def test_rigid_forward_16bit_channel_counts(c, phases, dtype):
+    """16-bit storage under rigid motion for every specialised channel count:
+    widths of whole 128-pixel segments (256, 1024) and a ragged tail (600);
+    a moving block makes some segments fall back to the one-pixel paths."""
+    dev = need_gpu()
+    rng = np.random.default_rng(20 + c + len(phases))
+    for h, w, px, py, rect in ((9, 256, 1.25, -0.5, None), (13, 600, -2.75, 3.5, None),
+                               (10, 1024, 0.3, 0.7, (2, 8, 300, 420, -9.0, 4.5))):
+        src = rng.random((2, c, h, w)).astype(np.float32)
+        mv = pan_field(2, h, w, px, py, rect)
+        announce("rigid 16-bit forward", c, phases, dtype, (h, w))
+        s = to_dev(src, dtype, dev)
+        m = torch.from_numpy(np.ascontiguousarray(mv)).to(dev)
+        out, mask, cnt = exw.warp(s, m, phases, return_mask=True, return_count=True)
+        torch.cuda.synchronize()
+        ref, ref_mask, ref_cnt = warp_oracle.forward(stored(src, dtype), mv, list(phases))
+        assert np.array_equal(mask.cpu().numpy(), ref_mask)
+        assert np.array_equal(cnt.cpu().numpy().astype(np.int64), ref_cnt)
+        assert_close_kernel(to_host(out), ref, dtype, f"rigid c={c} {dtype} {w}")
