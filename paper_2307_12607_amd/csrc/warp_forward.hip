@@ -68,6 +68,14 @@ __device__ __forceinline__ float shift_down1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
+// v from lane + 1, and `last` (a value read back from another lane) into
+// lane 63. Read-backs are taken outside divergent code: inside a branch of
+// lane 63 alone, the compiler may sink the load they read there, and the
+// lanes that were to load would not execute it.
+__device__ __forceinline__ float shift_down1_or(int last, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(last, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ void count_invalid(uint32_t *count, int64_t plane, bool inside,
                                               bool valid) {
     // One atomic per wavefront that saw invalid pixels (frame borders only).
@@ -157,12 +165,9 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
         T *fout = a.out + (static_cast<int64_t>(q.in) * KT + j) * CT * hw;
 #pragma unroll
         for (int ch = 0; ch < CT; ++ch) {
-            float b0 = shift_down1(a0[j][ch]), b1 = shift_down1(a1[j][ch]);
-            if (threadIdx.x == kTileW - 1) {
-                b0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), j * 2 * CT + ch));
-                b1 = __int_as_float(
-                    __builtin_amdgcn_readlane(__float_as_int(ex), j * 2 * CT + CT + ch));
-            }
+            const int e0 = __builtin_amdgcn_readlane(__float_as_int(ex), j * 2 * CT + ch);
+            const int e1 = __builtin_amdgcn_readlane(__float_as_int(ex), j * 2 * CT + CT + ch);
+            const float b0 = shift_down1_or(e0, a0[j][ch]), b1 = shift_down1_or(e1, a1[j][ch]);
             float acc = w00 * a0[j][ch];
             acc = fmaf(w01, b0, acc);
             acc = fmaf(w10, a1[j][ch], acc);
@@ -271,8 +276,8 @@ __device__ __forceinline__ void forward_row(const FwdArgs<T> &a, const PixelPos 
                 for (int ch = 0; ch < CT; ++ch) {
                     const float a0 = to_f32(*at(iplane[ch], r0 + xa));
                     const float a1 = to_f32(*at(iplane[ch], r1 + xa));
-                    float b0 = shift_down1(a0), b1 = shift_down1(a1);
-                    if (threadIdx.x == kTileW - 1) { b0 = e0[ch]; b1 = e1[ch]; }
+                    const float b0 = shift_down1_or(__float_as_int(e0[ch]), a0);
+                    const float b1 = shift_down1_or(__float_as_int(e1[ch]), a1);
                     float acc = w00 * a0;
                     acc = fmaf(w01, b0, acc);
                     acc = fmaf(w10, a1, acc);
@@ -428,11 +433,9 @@ __device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &
         T *fout = a.out + (static_cast<int64_t>(g.in) * KT + j) * CT * hw;
 #pragma unroll
         for (int ch = 0; ch < CT; ++ch) {
-            float n0 = shift_down1(s0[ch]), n1 = shift_down1(s1[ch]);
-            if (threadIdx.x == kTileW - 1) {
-                n0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), ch));
-                n1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), CT + ch));
-            }
+            const int e0 = __builtin_amdgcn_readlane(__float_as_int(ex), ch);
+            const int e1 = __builtin_amdgcn_readlane(__float_as_int(ex), CT + ch);
+            const float n0 = shift_down1_or(e0, s0[ch]), n1 = shift_down1_or(e1, s1[ch]);
             float acc0 = a00 * s0[ch];
             acc0 = fmaf(a01, t0[ch], acc0);
             acc0 = fmaf(a10, s1[ch], acc0);
