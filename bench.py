@@ -263,9 +263,34 @@ class Workload:
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) / reps * 1e3
         gbs = 8 * n * h * w / (us * 1e-6) / 1e9
+
+        # The same statistics folded by the recording forward from its own
+        # motion read: the forward's time with and without them, alternated.
+        s = self.sets[0]
+
+        def rec(stats):
+            exw.exw_warp_forward_batched_record(s["src"], s["mv"], self.phases, s["out"],
+                                                s["ws"], s["mask"], s["count"],
+                                                motion_stats=stats)
+        fused = {None: [], "stats": []}
+        for _ in range(3):
+            for key, stats in ((None, None), ("stats", out)):
+                for _ in range(3):
+                    rec(stats)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    rec(stats)
+                e1.record()
+                torch.cuda.synchronize()
+                fused[key].append(e0.elapsed_time(e1) / reps * 1e3)
+        plain_us, with_us = min(fused[None]), min(fused["stats"])
         return {"workload": f"config{self.spec.index}: motion statistics of {n}x{w}x{h}",
                 "us": round(us, 2), "alg_bytes": 8 * n * h * w, "gbs": round(gbs, 1),
-                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "fused_in_recording_forward": {
+                    "forward_us": round(plain_us, 2), "forward_with_stats_us": round(with_us, 2),
+                    "extra_us": round(with_us - plain_us, 2)}}
 
     def run_quality_and_chain(self, reps=5):
         """Frame quality (MSE/PSNR/SSIM) of the N*K predicted frames against the

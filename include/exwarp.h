@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define EXW_ABI_VERSION 1
+#define EXW_ABI_VERSION 2
 #define EXW_MAX_PHASES 4   /* K, phases fused into one launch */
 #define EXW_MAX_CHANNELS 64
 
@@ -113,11 +113,14 @@ exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t
                             const float *mv, float phase, void *out, uint8_t *mask,
                             void *stream);
 
-/* Bytes of device workspace exw_warp_backward_batched needs when grad_src is
- * requested: per row segment (64 output pixels of a row) a 16-byte tap box
- * and 16 bytes of tap offsets, 8 bytes per frame, and for EXW_F16/EXW_BF16 a
- * float32 image-gradient accumulator of 4*N*C*H*W bytes. Returns 0 for an
- * invalid dtype or an empty batch. */
+/* Bytes of device workspace exw_warp_backward_batched (and the training pair)
+ * needs when grad_src is requested: per row segment (64 output pixels of a
+ * row) a 16-byte tap box and 16 bytes of tap offsets, 8 bytes per frame, the
+ * recording forward's motion statistics (48 bytes per 128 x 4 tile of each
+ * frame, at least one per 2048 pixels and at most 256 per frame, plus 392
+ * bytes per frame for their fold), and for EXW_F16/EXW_BF16 a float32
+ * image-gradient accumulator of 4*N*C*H*W bytes. Returns 0 for an invalid
+ * dtype or an empty batch. */
 size_t exw_warp_backward_workspace_bytes(exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                                          int32_t w);
 
@@ -168,6 +171,16 @@ exw_status exw_warp_backward(const void *src, exw_dtype dtype, int32_t c, int32_
  *   h, w) bytes, 256-byte aligned, disjoint from every input and output;
  *   required unless the batch is empty). The outputs equal those of
  *   exw_warp_forward_batched.
+ *   motion_stats: optional [N, 4] float64 device output (8-byte aligned), or
+ *   NULL: the per-frame motion statistics of exw_motion_stats (mean and
+ *   population variance of each motion component, paper §IV-C, Eq. 1),
+ *   formed from the motion the forward reads anyway: each 128 x 4 tile folds
+ *   its values into a float64 (count, mean, M2) partial kept in the
+ *   workspace, and the partials of a frame are folded in a fixed order, so
+ *   the results are reproducible bit for bit (they may differ from
+ *   exw_motion_stats in the last bits: another order of the same fold).
+ *   With NULL the forward does none of this work. Requesting it for frames
+ *   with H = 0 or W = 0 is EXW_ERROR_INVALID_VALUE.
  * exw_warp_backward_batched_recorded: exw_warp_backward_batched, taking the
  *   footprint from `workspace` instead of computing it. The caller guarantees
  *   that the workspace was last written by exw_warp_forward_batched_record
@@ -180,8 +193,8 @@ exw_status exw_warp_forward_batched_record(const void *src, exw_dtype dtype, int
                                            int32_t h, int32_t w, const float *mv,
                                            const float *phases, int32_t k, void *out,
                                            uint8_t *mask, uint32_t *invalid_count,
-                                           void *workspace, size_t workspace_bytes,
-                                           void *stream);
+                                           double *motion_stats, void *workspace,
+                                           size_t workspace_bytes, void *stream);
 
 exw_status exw_warp_backward_batched_recorded(const void *src, exw_dtype dtype, int32_t n,
                                               int32_t c, int32_t h, int32_t w, const float *mv,

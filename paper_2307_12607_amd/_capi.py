@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libexwarp.so")
 
 EXW_F32, EXW_F16, EXW_BF16 = 0, 1, 2
 EXW_SUCCESS, EXW_ERROR_INVALID_VALUE, EXW_ERROR_UNSUPPORTED, EXW_ERROR_LAUNCH = 0, 1, 2, 3
-EXW_ABI_VERSION = 1
+EXW_ABI_VERSION = 2
 EXW_MAX_PHASES = 4
 EXW_MAX_CHANNELS = 64
 EXW_NO_ALLOC_SCRATCH_BYTES = 1 << 20
@@ -38,7 +38,8 @@ SIGNATURES = {
     "exw_warp_backward": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _p, _f, _p, _p, _p,
                                          _p, _sz, _p]),
     "exw_warp_forward_batched_record": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _i32,
-                                                       _p, _p, _i32, _p, _p, _p, _p, _sz, _p]),
+                                                       _p, _p, _i32, _p, _p, _p, _p, _p, _sz,
+                                                       _p]),
     "exw_warp_backward_batched_recorded": (ctypes.c_int, [_p, ctypes.c_int, _i32, _i32, _i32, _i32,
                                                           _p, _p, _i32, _p, _p, _p, _p, _sz, _p]),
     "exw_motion_stats_workspace_bytes": (_sz, [_i32, _i32, _i32]),

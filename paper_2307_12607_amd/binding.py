@@ -86,11 +86,13 @@ def exw_warp_forward_batched(src: torch.Tensor, mv: torch.Tensor, phases, out: t
 def exw_warp_forward_batched_record(src: torch.Tensor, mv: torch.Tensor, phases, out: torch.Tensor,
                                     workspace: torch.Tensor, mask: Optional[torch.Tensor] = None,
                                     invalid_count: Optional[torch.Tensor] = None,
+                                    motion_stats: Optional[torch.Tensor] = None,
                                     stream=None) -> None:
     """exw_warp_forward_batched, also leaving the adjoint's footprint of this
     motion and these phases in ``workspace`` (a byte tensor of at least
     ``exw_warp_backward_workspace_bytes`` bytes) for
-    exw_warp_backward_batched_recorded."""
+    exw_warp_backward_batched_recorded; with ``motion_stats`` ([N,4] float64)
+    also the per-frame motion statistics, from the same motion read."""
     dev = src.device
     _dev(src, "src", dev)
     n, c, h, w = src.shape
@@ -99,11 +101,12 @@ def exw_warp_forward_batched_record(src: torch.Tensor, mv: torch.Tensor, phases,
     _expect(out, "out", (n, k, c, h, w), src.dtype, dev)
     _expect(mask, "mask", (n, k, h, w), torch.uint8, dev)
     _expect(invalid_count, "invalid_count", (n, k), torch.int32, dev)
+    _expect(motion_stats, "motion_stats", (n, 4), torch.float64, dev)
     _dev(workspace, "workspace", dev)
     st = lib().exw_warp_forward_batched_record(
         _ptr(src), exw_dtype(src.dtype), n, c, h, w, _ptr(mv), arr, k, _ptr(out), _ptr(mask),
-        _ptr(invalid_count), _ptr(workspace), workspace.numel() * workspace.element_size(),
-        _stream(dev, stream))
+        _ptr(invalid_count), _ptr(motion_stats), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(dev, stream))
     check(st, "exw_warp_forward_batched_record")
 
 

@@ -151,7 +151,7 @@ exw_status launched(hipError_t e, const char *what) {
 
 // Byte offsets of the adjoint's scratch inside the caller's workspace.
 struct WsLayout {
-    size_t boxes, info, accum, total;
+    size_t boxes, info, stats, accum, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -160,7 +160,8 @@ WsLayout workspace_layout(int dtype, int n, int c, int h, int w) {
     WsLayout l;
     l.boxes = 0;
     l.info = align_up(exw::backward_box_bytes(n, h, w));
-    l.accum = align_up(l.info + exw::backward_info_bytes(n));
+    l.stats = align_up(l.info + exw::backward_info_bytes(n));
+    l.accum = align_up(l.stats + exw::record_stats_bytes(n, h, w));
     const size_t accum_bytes =
         dtype == EXW_F32 ? 0 : size_t(n) * size_t(c) * size_t(h) * size_t(w) * sizeof(float);
     l.total = l.accum + accum_bytes;
@@ -177,13 +178,17 @@ WsLayout workspace_layout(int dtype, int n, int c, int h, int w) {
 // motion and these phases in the caller's adjoint workspace.
 exw_status forward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                         int32_t w, const float *mv, const float *phases, int32_t k, void *out,
-                        uint8_t *mask, uint32_t *invalid_count, void *workspace,
-                        size_t workspace_bytes, bool record, void *stream) {
+                        uint8_t *mask, uint32_t *invalid_count, double *motion_stats,
+                        void *workspace, size_t workspace_bytes, bool record, void *stream) {
     Checked ck;
     EXW_TRY(check_common(dtype, n, c, h, w, phases, k, &ck));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint64_t nk = uint64_t(n) * uint64_t(k);
     EXW_TRY(check_ptr("invalid_count", invalid_count, 4, false));
+    EXW_TRY(check_ptr("motion_stats", motion_stats, 8, false));
+    if (motion_stats && n > 0 && (h == 0 || w == 0))
+        return fail(EXW_ERROR_INVALID_VALUE,
+                    "motion_stats of empty frames has no variance (h=%d, w=%d)", h, w);
     if (ck.empty) {
         if (invalid_count && nk > 0)
             return launched(exw::launch_zero_u32(invalid_count, int64_t(nk), st), "zero count");
@@ -206,15 +211,17 @@ exw_status forward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c, 
     const Span outs[] = {span("out", out, ck.out_elems * ck.esize),
                          span("mask", mask, nk * ck.hw),
                          span("invalid_count", invalid_count, nk * 4),
-                         span("workspace", record ? workspace : nullptr, ws_need)};
-    EXW_TRY(check_disjoint(outs, 4, ins, 2));
+                         span("workspace", record ? workspace : nullptr, ws_need),
+                         span("motion_stats", motion_stats, uint64_t(n) * 4u * 8u)};
+    EXW_TRY(check_disjoint(outs, 5, ins, 2));
     if (!record)
         return launched(exw::launch_forward(dtype, src, mv, ck.shape, out, mask, invalid_count, st),
                         "warp forward launch");
     char *base = static_cast<char *>(workspace);
-    const exw::BwdWorkspace ws{base + lay.boxes, base + lay.info, nullptr, false};
+    const exw::BwdWorkspace ws{base + lay.boxes, base + lay.info, nullptr, false,
+                               base + lay.stats};
     return launched(exw::launch_forward_record(dtype, src, mv, ck.shape, out, mask, invalid_count,
-                                               ws, st),
+                                               ws, motion_stats, st),
                     "warp forward launch");
 }
 
@@ -248,7 +255,7 @@ exw_status backward_impl(const void *src, exw_dtype dtype, int32_t n, int32_t c,
                          span("grad_mv", grad_mv, ck.mv_elems * 4),
                          span("workspace", needs_ws ? workspace : nullptr, ws_need)};
     EXW_TRY(check_disjoint(outs, 3, ins, 3));
-    exw::BwdWorkspace ws{nullptr, nullptr, nullptr, recorded};
+    exw::BwdWorkspace ws{nullptr, nullptr, nullptr, recorded, nullptr};
     if (needs_ws) {
         char *base = static_cast<char *>(workspace);
         ws.boxes = base + lay.boxes;
@@ -288,17 +295,17 @@ exw_status exw_warp_forward_batched(const void *src, exw_dtype dtype, int32_t n,
                                     int32_t k, void *out, uint8_t *mask,
                                     uint32_t *invalid_count, void *stream) {
     return forward_impl(src, dtype, n, c, h, w, mv, phases, k, out, mask, invalid_count, nullptr,
-                        0, false, stream);
+                        nullptr, 0, false, stream);
 }
 
 exw_status exw_warp_forward_batched_record(const void *src, exw_dtype dtype, int32_t n, int32_t c,
                                            int32_t h, int32_t w, const float *mv,
                                            const float *phases, int32_t k, void *out,
                                            uint8_t *mask, uint32_t *invalid_count,
-                                           void *workspace, size_t workspace_bytes,
-                                           void *stream) {
+                                           double *motion_stats, void *workspace,
+                                           size_t workspace_bytes, void *stream) {
     return forward_impl(src, dtype, n, c, h, w, mv, phases, k, out, mask, invalid_count,
-                        workspace, workspace_bytes, true, stream);
+                        motion_stats, workspace, workspace_bytes, true, stream);
 }
 
 exw_status exw_warp_forward(const void *src, exw_dtype dtype, int32_t c, int32_t h, int32_t w,

@@ -29,7 +29,13 @@ struct BwdWorkspace {
     void *info;      // per frame: reach of the segments, far flag
     float *accum32;  // float32 image-gradient accumulator (16-bit storage only)
     bool recorded;   // boxes and info already hold the footprint of this motion and these phases
+    void *stat_parts;  // motion-statistics partials of the recording forward (or NULL)
 };
+
+// Bytes of the recording forward's motion statistics for N frames of H x W:
+// 48 bytes per 128 x 4 tile of each frame, the fold's 384 bytes of slots and
+// 8 bytes of counters per frame.
+size_t record_stats_bytes(int n, int h, int w);
 
 size_t backward_box_bytes(int n, int h, int w);
 size_t backward_info_bytes(int n);
@@ -43,7 +49,11 @@ hipError_t launch_footprint(const float *mv, const WarpShape &s, const BwdWorksp
 
 // The per-frame figures of ws.info (reach of the near segments, far flag)
 // from the boxes already in ws.boxes; ws.info must hold zeros.
-hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, hipStream_t stream);
+// The per-frame figures of the footprint records; with `fold`, the same
+// launch also folds the recording forward's motion-statistics partials.
+struct TileFold;
+hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, const TileFold *fold,
+                              hipStream_t stream);
 
 hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t stream);
 
@@ -51,10 +61,12 @@ hipError_t launch_forward(int dtype, const void *src, const float *mv, const War
                           void *out, uint8_t *mask, uint32_t *count, hipStream_t stream);
 
 // The forward, also recording the adjoint's footprint into ws (when the
-// adjoint of this channel count reads it).
+// adjoint of this channel count reads it) and, when motion_stats is not NULL,
+// the per-frame motion statistics [N][4] (partials in ws.stat_parts).
 hipError_t launch_forward_record(int dtype, const void *src, const float *mv, const WarpShape &s,
                                  void *out, uint8_t *mask, uint32_t *count,
-                                 const BwdWorkspace &ws, hipStream_t stream);
+                                 const BwdWorkspace &ws, double *motion_stats,
+                                 hipStream_t stream);
 
 // grad_src / grad_mv may each be NULL (not requested). The workspace is used
 // only when grad_src is requested.

@@ -14,6 +14,7 @@
 #include <mutex>
 
 #include "launch.h"
+#include "moments.h"
 
 namespace exw {
 namespace {
@@ -22,35 +23,6 @@ constexpr int kStatThreads = 256;
 constexpr int kChunk = 8;                          // values per thread, per component
 constexpr int kSpan = kStatThreads * kChunk;       // pixels per workgroup pass
 constexpr int kMaxParts = 256;                     // workgroups per frame, at most
-
-struct Moments {
-    double n, mean, m2;
-};
-
-__device__ __forceinline__ Moments fold(const Moments &a, const Moments &b) {
-    if (b.n == 0.0) return a;
-    if (a.n == 0.0) return b;
-    const double n = a.n + b.n;
-    const double d = b.mean - a.mean;
-    const double fb = b.n / n;
-    return Moments{n, a.mean + d * fb, a.m2 + b.m2 + d * d * a.n * fb};
-}
-
-__device__ __forceinline__ Moments shfl_xor(const Moments &m, int mask) {
-    return Moments{__shfl_xor(m.n, mask), __shfl_xor(m.mean, mask), __shfl_xor(m.m2, mask)};
-}
-
-// Fold over the 64 lanes of a wavefront (butterfly: every lane ends with the
-// same value, built in the same order).
-__device__ __forceinline__ Moments wave_fold(Moments m) {
-#pragma unroll
-    for (int mask = 1; mask < 64; mask <<= 1) {
-        const Moments o = shfl_xor(m, mask);
-        // lower lane of each pair first, so both lanes compute the same fold
-        m = (__lane_id() & mask) ? fold(o, m) : fold(m, o);
-    }
-    return m;
-}
 
 __device__ __forceinline__ Moments chunk_moments(const float (&x)[kChunk], int count) {
     if (count <= 0) return Moments{0.0, 0.0, 0.0};
@@ -174,18 +146,31 @@ size_t motion_stats_workspace_bytes(int n, int h, int w) {
            parts_for(static_cast<int64_t>(h) * w);
 }
 
-hipError_t launch_motion_stats(const float *mv, int n, int h, int w, double *stats,
-                               void *workspace, hipStream_t stream) {
+int motion_stats_parts(int h, int w) { return parts_for(static_cast<int64_t>(h) * w); }
+
+hipError_t launch_motion_moments(const float *mv, int n, int h, int w, Moments *partial,
+                                 hipStream_t stream) {
     const int64_t hw = static_cast<int64_t>(h) * w;
     const int parts = parts_for(hw);
-    Moments *partial = static_cast<Moments *>(workspace);
     hipLaunchKernelGGL(motion_moments_kernel, dim3(static_cast<unsigned>(n) * parts),
                        dim3(kStatThreads), 0, stream, mv, hw, parts, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_motion_stats_fold(const Moments *partial, int n, int parts, double *stats,
+                                    hipStream_t stream) {
     hipLaunchKernelGGL(motion_stats_final_kernel, dim3(static_cast<unsigned>(n) * 2), dim3(64), 0,
                        stream, partial, parts, stats);
     return hipGetLastError();
+}
+
+hipError_t launch_motion_stats(const float *mv, int n, int h, int w, double *stats,
+                               void *workspace, hipStream_t stream) {
+    Moments *partial = static_cast<Moments *>(workspace);
+    hipError_t e = launch_motion_moments(mv, n, h, w, partial, stream);
+    if (e != hipSuccess) return e;
+    return launch_motion_stats_fold(partial, n, parts_for(static_cast<int64_t>(h) * w), stats,
+                                    stream);
 }
 
 }  // namespace exw

@@ -28,6 +28,7 @@
 //     float32 workspace and pass 4 rounds it into the output.
 #include "footprint.h"
 #include "launch.h"
+#include "moments.h"
 #include "warp_common.h"
 
 namespace exw {
@@ -136,9 +137,17 @@ __global__ __launch_bounds__(kThreads) void footprint_kernel(const float *mv, Bo
 // few of them, and no wavefront waits on more than one).
 constexpr int kReachPerThread = 4;
 
+// Workgroups past the reduction's (n * blocks_per_frame) fold the recording
+// forward's motion-statistics partials.
+static_assert(kThreads == kTileFoldThreads, "the statistics fold runs in these workgroups");
 __global__ __launch_bounds__(kThreads) void frame_reach_kernel(const Box *boxes, FrameInfo *info,
                                                                int h, int segs,
-                                                               int blocks_per_frame) {
+                                                               int blocks_per_frame,
+                                                               int reach_blocks, TileFold fold) {
+    if (static_cast<int>(blockIdx.x) >= reach_blocks) {  // workgroup-uniform
+        fold_tile_share(fold, static_cast<int>(blockIdx.x) - reach_blocks);
+        return;
+    }
     __shared__ int red[2][kThreads / kSegW];
     const int in = static_cast<int>(blockIdx.x) / blocks_per_frame;
     const int part = static_cast<int>(blockIdx.x) - in * blocks_per_frame;
@@ -1053,15 +1062,20 @@ size_t backward_info_bytes(int n) { return sizeof(FrameInfo) * static_cast<size_
 
 bool backward_uses_footprint(int c) { return c == 1 || c == 2 || c == 3 || c == 4 || c == 12; }
 
-hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, hipStream_t stream) {
+hipError_t launch_frame_reach(const WarpShape &s, const BwdWorkspace &ws, const TileFold *fold,
+                              hipStream_t stream) {
     const int segs = (s.w + kSegW - 1) / kSegW;
     const int64_t per_frame = static_cast<int64_t>(s.h) * segs;
     const int bx = static_cast<int>((per_frame + kThreads * kReachPerThread - 1) /
                                     (kThreads * kReachPerThread));
     // n * bx < 2^31: the C ABI bounds the batch's 64 x 4 tiles below 2^31
-    hipLaunchKernelGGL(frame_reach_kernel, dim3(static_cast<unsigned>(static_cast<int64_t>(s.n) * bx)),
+    const int64_t reach_blocks = static_cast<int64_t>(s.n) * bx;
+    const int64_t fold_blocks = fold ? static_cast<int64_t>(s.n) * 2 * kTileFoldParts : 0;
+    const TileFold none{nullptr, 0, nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL(frame_reach_kernel, dim3(static_cast<unsigned>(reach_blocks + fold_blocks)),
                        dim3(kThreads), 0, stream, reinterpret_cast<const Box *>(ws.boxes),
-                       reinterpret_cast<FrameInfo *>(ws.info), s.h, segs, bx);
+                       reinterpret_cast<FrameInfo *>(ws.info), s.h, segs, bx,
+                       static_cast<int>(reach_blocks), fold ? *fold : none);
     return hipGetLastError();
 }
 

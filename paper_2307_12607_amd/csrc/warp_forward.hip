@@ -25,6 +25,7 @@
 // adjoint of a training step can skip its first pass.
 #include "footprint.h"
 #include "launch.h"
+#include "moments.h"
 #include "warp_common.h"
 
 namespace exw {
@@ -55,6 +56,11 @@ struct FwdArgs {
     SegOffsets *offs;
     uint32_t *info_words;  // the per-frame figures (2 words per frame), zeroed by block 0
     int segs;
+    // Motion-statistics partials ([N][2][tiles per frame], the STATS
+    // instantiation): one per 128 x 4 tile and motion component; and the
+    // fold's counters ([N][2]), zeroed by block 0 for the pass that follows.
+    Moments *stat_parts;
+    uint32_t *stat_counters;
 };
 
 struct PixelPos {
@@ -372,21 +378,20 @@ __device__ __forceinline__ void store_pair(T *p, float a, float b) {
 // from one load spread over lanes 0 .. 2C-1), and both outputs of a plane are
 // stored at once - half the memory instructions per pixel of the one-pixel
 // path. Phases with the offsets of the previous phase reuse its samples. The
-// blend is that of the one-pixel path, term for term. Returns false, having
-// written nothing, when the segment is not uniform; else true, with the
-// offsets (ceil(s_k u), ceil(s_k v)) of every phase in (orx, ory).
-template <typename T, int CT, int KT>
-__device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &g, int (&orx)[KT],
-                                             int (&ory)[KT]) {
+// blend is that of the one-pixel path, term for term. (u0, v0), (u1, v1): the
+// motion of the lane's two pixels; after_first_loads() runs once the first
+// phase's gathers are issued. Returns false, having written nothing, when
+// the segment is not uniform; else true, with the offsets (ceil(s_k u),
+// ceil(s_k v)) of every phase in (orx, ory).
+template <typename T, int CT, int KT, typename Hook>
+__device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &g, float u0,
+                                             float u1, float v0, float v1, int (&orx)[KT],
+                                             int (&ory)[KT], Hook &&after_first_loads) {
     const int w = a.w, h = a.h, y = g.y;
     const int64_t hw = static_cast<int64_t>(h) * w;
     const uint32_t hw32 = static_cast<uint32_t>(hw);  // the frame spans less than 4 GB
     const int x = g.sx0 + 2 * static_cast<int>(threadIdx.x);
     const uint32_t p = static_cast<uint32_t>(y) * static_cast<uint32_t>(w) + static_cast<uint32_t>(x);
-    const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
-    float u0, u1, v0, v1;
-    load_pair(at(mu, p), u0, u1);
-    load_pair(at(mu + hw, p), v0, v1);
     float fx0[KT], fx1[KT], fy0[KT], fy1[KT];
     int rx[KT], ry[KT];
     bool uni = true;
@@ -425,6 +430,7 @@ __device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &
                 load_pair(at(fin, ch * hw32 + r1 + c), s1[ch], t1[ch]);
             }
         }
+        if (j == 0) after_first_loads();  // work that overlaps the gathers in flight
         // pixel 2j: taps (s, t); pixel 2j+1: taps (t, next lane's s)
         const float a00 = (1.0f - fx0[j]) * (1.0f - fy0[j]), a01 = fx0[j] * (1.0f - fy0[j]);
         const float a10 = (1.0f - fx0[j]) * fy0[j], a11 = fx0[j] * fy0[j];
@@ -504,22 +510,172 @@ __device__ __forceinline__ void record_rows(const FwdArgs<T> &a, const SegPos &g
     }
 }
 
+// Motion statistics of the block's tile (the recording forward, STATS). Every
+// wavefront of the block takes the same shift (u_0, v_0), the motion of the
+// tile's first pixel, and forms the float64 sums of its pixels' differences
+// from it and of their squares (differences and squares of float32 values are
+// exact in float64) from the motion it holds two pixels per lane for the
+// two-pixel path. After the block's other work one lane adds the four
+// wavefronts' sums in order and turns them into the tile's (count, mean, M2):
+// mean = u_0 + S1 / n, M2 = S2 - S1^2 / n, which loses at most a factor of the
+// tile's 512 pixels to cancellation against the two-pass value.
+struct WaveSums {
+    double n, s[4];  // count; S1(u), S2(u), S1(v), S2(v)
+};
+
+__device__ __forceinline__ WaveSums (&stat_slots())[kTileH] {
+    __shared__ WaveSums slots[kTileH];
+    return slots;
+}
+
+// v from another lane (DPP control CTRL on both halves); 0.0 where the
+// source lane lies outside the row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
+// The four sums over the wavefront, transposed: the first two exchange steps
+// halve the values each lane carries (lane pairs, then quads), so the steps
+// after them move one value instead of four. Afterwards lanes 12..15 of a row
+// hold the sums of slots 0, 2, 1, 3 (a fixed order of additions).
+__device__ __forceinline__ double wave_sums4(double a0, double a1, double a2, double a3) {
+    const int lane = static_cast<int>(threadIdx.x);
+    const bool odd = lane & 1, hb = (lane >> 1) & 1;
+    // pairs (quad_perm 1,0,3,2): even lanes keep slots 0,1, odd lanes 2,3
+    const double b0 = (odd ? a2 : a0) + dpp_f64<0xB1>(odd ? a0 : a2);
+    const double b1 = (odd ? a3 : a1) + dpp_f64<0xB1>(odd ? a1 : a3);
+    // quads (quad_perm 2,3,0,1): lane q of a quad keeps slot 0, 2, 1, 3
+    double c = (hb ? b1 : b0) + dpp_f64<0x4E>(hb ? b0 : b1);
+    // the four quads of a row into its lanes 12..15 (row_shr 4, row_shr 8)
+    c += dpp_f64<0x114>(c);
+    c += dpp_f64<0x118>(c);
+    // the four rows
+    c += __shfl_xor(c, 16);
+    c += __shfl_xor(c, 32);
+    return c;
+}
+
+__device__ __forceinline__ void wave_motion_sums(float su, float sv, float u0, float u1, float v0,
+                                                 float v1, bool in0, bool in1) {
+    const double n = static_cast<double>(__popcll(__ballot(in0)) + __popcll(__ballot(in1)));
+    double s1u = 0.0, s2u = 0.0, s1v = 0.0, s2v = 0.0;
+    if (in0) {
+        const double du = static_cast<double>(u0) - su, dv = static_cast<double>(v0) - sv;
+        s1u += du; s2u += du * du; s1v += dv; s2v += dv * dv;
+    }
+    if (in1) {
+        const double du = static_cast<double>(u1) - su, dv = static_cast<double>(v1) - sv;
+        s1u += du; s2u += du * du; s1v += dv; s2v += dv * dv;
+    }
+    const double t = wave_sums4(s1u, s2u, s1v, s2v);  // every lane is active here
+    const int lane = static_cast<int>(threadIdx.x);
+    if (lane >= 12 && lane < 16) {
+        const int q = lane - 12;
+        stat_slots()[threadIdx.y].s[(q & 1) * 2 + (q >> 1)] = t;
+        if (q == 0) stat_slots()[threadIdx.y].n = n;
+    }
+}
+
+// After the block's other work: every thread reaches the barrier.
+template <typename T>
+__device__ __forceinline__ void block_motion_partial(const FwdArgs<T> &a, const SegPos &g,
+                                                     float su, float sv) {
+    __syncthreads();
+    if (threadIdx.y == 0 && threadIdx.x < 2) {
+        const bool vc = threadIdx.x == 1;
+        double n = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int wv = 0; wv < kTileH; ++wv) {
+            const WaveSums &q = stat_slots()[wv];
+            n += q.n;
+            s1 += q.s[vc ? 2 : 0];
+            s2 += q.s[vc ? 3 : 1];
+        }
+        const double shift = vc ? sv : su;
+        // a block's tile always holds its first pixel: n >= 1
+        const Moments m{n, shift + s1 / n, s2 - s1 * s1 / n};
+        const int per_frame = a.tiles_x * a.tiles_y;
+        const int tile = xcd_tile_index(blockIdx.x, gridDim.x) - g.in * per_frame;
+        a.stat_parts[(static_cast<int64_t>(g.in) * 2 + threadIdx.x) * per_frame + tile] = m;
+    }
+}
+
 // One 128-pixel row segment per wavefront: two pixels per lane when the whole
 // segment is uniform in every phase, otherwise the one-pixel paths on each
-// half. REC: also write the adjoint's footprint records of the two segments.
-template <typename T, int CT, int KT, bool REC>
+// half. REC: also write the adjoint's footprint records of the two segments;
+// STATS (with REC): also the tile's motion-statistics partial.
+template <typename T, int CT, int KT, bool REC, bool STATS>
 __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
     if constexpr (REC) {  // ready for the reduction pass that follows (no launch of its own)
-        if (blockIdx.x == 0 && threadIdx.y == 0)
+        if (blockIdx.x == 0 && threadIdx.y == 0) {
             for (int i = threadIdx.x; i < 2 * a.n; i += kTileW) a.info_words[i] = 0u;
+            if constexpr (STATS)
+                for (int i = threadIdx.x; i < 2 * a.n; i += kTileW) a.stat_counters[i] = 0u;
+        }
     }
     const SegPos g = decode_segment(a.tiles_x, a.tiles_y);
-    if constexpr (2 * CT * KT <= kTileW) {
+    const bool full = g.y < a.h && g.sx0 + kSegPair <= a.w;  // wave-uniform
+    if constexpr (STATS) {
+        // the motion of the wavefront's pixels 2j, 2j+1 (lane j), for the
+        // statistics and the two-pixel path alike
+        const int x = g.sx0 + 2 * static_cast<int>(threadIdx.x);
+        const bool in0 = g.y < a.h && x < a.w, in1 = g.y < a.h && x + 1 < a.w;
+        const int64_t hw = static_cast<int64_t>(a.h) * a.w;
+        const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
+        const uint32_t p = static_cast<uint32_t>(g.y) * static_cast<uint32_t>(a.w) +
+                           static_cast<uint32_t>(x);
+        // the shift: the motion of the tile's first pixel (wave-uniform address)
+        const int y0 = __builtin_amdgcn_readfirstlane(g.y - static_cast<int>(threadIdx.y));
+        const uint32_t p0 = static_cast<uint32_t>(y0) * static_cast<uint32_t>(a.w) +
+                            static_cast<uint32_t>(g.sx0);
+        const float su = *at(mu, p0), sv = *at(mu + hw, p0);
+        float u0 = 0.0f, u1 = 0.0f, v0 = 0.0f, v1 = 0.0f;
+        if (full) {
+            load_pair(at(mu, p), u0, u1);
+            load_pair(at(mu + hw, p), v0, v1);
+        } else {
+            if (in0) { u0 = *at(mu, p); v0 = *at(mu + hw, p); }
+            if (in1) { u1 = *at(mu, p + 1); v1 = *at(mu + hw, p + 1); }
+        }
+        auto sums = [&] { wave_motion_sums(su, sv, u0, u1, v0, v1, in0, in1); };
+        bool done = false;
+        if constexpr (2 * CT * KT <= kTileW) {
+            int rx[KT], ry[KT];
+            // (the sums are formed while the first gathers are in flight)
+            if (a.frame_32bit && full &&
+                pair_uniform<T, CT, KT>(a, g, u0, u1, v0, v1, rx, ry, sums)) {
+                record_pair<T, KT>(a, g, rx, ry);
+                done = true;
+            }
+        }
+        if (!done) {
+            sums();
+#pragma unroll 1
+            for (int half = 0; half < 2; ++half)
+                forward_row<T, CT, KT>(a, half_pixel(g, half, a.w, a.h));
+            record_rows<T, KT>(a, g);
+        }
+        block_motion_partial<T>(a, g, su, sv);
+        return;
+    } else if constexpr (2 * CT * KT <= kTileW) {
         int rx[KT], ry[KT];
-        if (a.frame_32bit && g.y < a.h && g.sx0 + kSegPair <= a.w &&  // wave-uniform
-            pair_uniform<T, CT, KT>(a, g, rx, ry)) {
-            if constexpr (REC) record_pair<T, KT>(a, g, rx, ry);
-            return;
+        if (a.frame_32bit && full) {
+            const int64_t hw = static_cast<int64_t>(a.h) * a.w;
+            const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
+            const uint32_t p = static_cast<uint32_t>(g.y) * static_cast<uint32_t>(a.w) +
+                               static_cast<uint32_t>(g.sx0 + 2 * static_cast<int>(threadIdx.x));
+            float u0, u1, v0, v1;
+            load_pair(at(mu, p), u0, u1);
+            load_pair(at(mu + hw, p), v0, v1);
+            if (pair_uniform<T, CT, KT>(a, g, u0, u1, v0, v1, rx, ry, [] {})) {
+                if constexpr (REC) record_pair<T, KT>(a, g, rx, ry);
+                return;
+            }
         }
     }
 #pragma unroll 1
@@ -584,6 +740,32 @@ __global__ void zero_u32_kernel(uint32_t *p, int64_t n) {
         p[t] = 0u;
 }
 
+// The statistics region of the adjoint's workspace: the tile partials
+// ([N][2][parts], parts = the larger of the tile count and the statistics
+// pass's partial count, so either route fits), the fold's slots
+// ([N][2][kTileFoldParts]) and its counters ([N][2]).
+struct StatsRegion {
+    Moments *parts, *slots;
+    uint32_t *counters;
+    int tiles;
+    size_t bytes;
+};
+
+StatsRegion stats_region(void *base, int n, int h, int w) {
+    StatsRegion r;
+    r.tiles = ((w + kSegPair - 1) / kSegPair) * ((h + kTileH - 1) / kTileH);
+    const int stat_parts = motion_stats_parts(h, w);
+    const size_t parts = static_cast<size_t>(r.tiles > stat_parts ? r.tiles : stat_parts);
+    const size_t parts_bytes = sizeof(Moments) * 2 * static_cast<size_t>(n) * parts;
+    const size_t slot_bytes = sizeof(Moments) * 2 * static_cast<size_t>(n) * kTileFoldParts;
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+    r.parts = reinterpret_cast<Moments *>(b);
+    r.slots = reinterpret_cast<Moments *>(b + parts_bytes);
+    r.counters = reinterpret_cast<uint32_t *>(b + parts_bytes + slot_bytes);
+    r.bytes = parts_bytes + slot_bytes + sizeof(uint32_t) * 2 * static_cast<size_t>(n);
+    return r;
+}
+
 template <typename T>
 FwdArgs<T> make_args(const void *src, const float *mv, const WarpShape &s, void *out,
                      uint8_t *mask, uint32_t *count) {
@@ -602,24 +784,28 @@ FwdArgs<T> make_args(const void *src, const float *mv, const WarpShape &s, void 
     a.offs = nullptr;
     a.info_words = nullptr;
     a.segs = (s.w + kSegW - 1) / kSegW;
+    a.stat_parts = nullptr;
+    a.stat_counters = nullptr;
     return a;
 }
 
-template <typename T, int CT, bool REC>
+template <typename T, int CT, bool REC, bool STATS>
 hipError_t launch_ckr(const FwdArgs<T> &a, dim3 grid, hipStream_t st) {
     const dim3 block(kTileW, kTileH);
     switch (a.k) {
-    case 1: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 1, REC>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 2, REC>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 3, REC>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 4, REC>), grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 1, REC, STATS>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 2, REC, STATS>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 3, REC, STATS>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((warp_forward_kernel<T, CT, 4, REC, STATS>), grid, block, 0, st, a); break;
     }
     return hipGetLastError();
 }
 
 template <typename T, int CT>
 hipError_t launch_ck(const FwdArgs<T> &a, dim3 grid, hipStream_t st) {
-    return a.boxes ? launch_ckr<T, CT, true>(a, grid, st) : launch_ckr<T, CT, false>(a, grid, st);
+    if (!a.boxes) return launch_ckr<T, CT, false, false>(a, grid, st);
+    return a.stat_parts ? launch_ckr<T, CT, true, true>(a, grid, st)
+                        : launch_ckr<T, CT, true, false>(a, grid, st);
 }
 
 // Whether the specialised kernel (which can record the footprint) serves C.
@@ -634,6 +820,11 @@ hipError_t launch_typed(const void *src, const float *mv, const WarpShape &s, vo
         a.boxes = reinterpret_cast<Box *>(rec->boxes);
         a.offs = reinterpret_cast<SegOffsets *>(a.boxes + static_cast<size_t>(s.n) * s.h * a.segs);
         a.info_words = reinterpret_cast<uint32_t *>(rec->info);
+        if (rec->stat_parts) {
+            const StatsRegion r = stats_region(rec->stat_parts, s.n, s.h, s.w);
+            a.stat_parts = r.parts;
+            a.stat_counters = r.counters;
+        }
     }
     const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(a.tiles_x) * a.tiles_y * s.n));
     if (specialised(s.c, s.w)) {
@@ -672,26 +863,42 @@ hipError_t launch_forward(int dtype, const void *src, const float *mv, const War
     }
 }
 
+size_t record_stats_bytes(int n, int h, int w) {
+    return stats_region(nullptr, n, h, w).bytes;
+}
+
 hipError_t launch_forward_record(int dtype, const void *src, const float *mv, const WarpShape &s,
                                  void *out, uint8_t *mask, uint32_t *count,
-                                 const BwdWorkspace &ws, hipStream_t stream) {
+                                 const BwdWorkspace &ws, double *motion_stats,
+                                 hipStream_t stream) {
+    const StatsRegion r = stats_region(ws.stat_parts, s.n, s.h, s.w);
     if (!backward_uses_footprint(s.c) || !specialised(s.c, s.w)) {
         // the adjoint reads no records, or the kernel that serves this shape
         // does not write them: the plain forward, then the footprint pass
+        // (and the statistics pass)
         hipError_t e = launch_forward(dtype, src, mv, s, out, mask, count, stream);
-        if (e != hipSuccess || !backward_uses_footprint(s.c)) return e;
-        return launch_footprint(mv, s, ws, stream);
+        if (e == hipSuccess && backward_uses_footprint(s.c)) e = launch_footprint(mv, s, ws, stream);
+        if (e != hipSuccess || !motion_stats) return e;
+        e = launch_motion_moments(mv, s.n, s.h, s.w, r.parts, stream);
+        if (e != hipSuccess) return e;
+        return launch_motion_stats_fold(r.parts, s.n, motion_stats_parts(s.h, s.w), motion_stats,
+                                        stream);
     }
     hipError_t e = count ? launch_zero_u32(count, static_cast<int64_t>(s.n) * s.k, stream)
                          : hipSuccess;
     if (e != hipSuccess) return e;
+    BwdWorkspace rec = ws;
+    if (!motion_stats) rec.stat_parts = nullptr;  // the instantiation without statistics
     switch (dtype) {
-    case 0: e = launch_typed<float>(src, mv, s, out, mask, count, &ws, stream); break;
-    case 1: e = launch_typed<_Float16>(src, mv, s, out, mask, count, &ws, stream); break;
-    default: e = launch_typed<__bf16>(src, mv, s, out, mask, count, &ws, stream); break;
+    case 0: e = launch_typed<float>(src, mv, s, out, mask, count, &rec, stream); break;
+    case 1: e = launch_typed<_Float16>(src, mv, s, out, mask, count, &rec, stream); break;
+    default: e = launch_typed<__bf16>(src, mv, s, out, mask, count, &rec, stream); break;
     }
     if (e != hipSuccess) return e;
-    return launch_frame_reach(s, ws, stream);
+    if (!motion_stats) return launch_frame_reach(s, ws, nullptr, stream);
+    // the tile partials are folded inside the reduction of the footprint records
+    const TileFold fold{r.parts, r.tiles, r.slots, r.counters, motion_stats};
+    return launch_frame_reach(s, ws, &fold, stream);
 }
 
 }  // namespace exw

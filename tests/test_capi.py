@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = _capi.lib()
-    assert L.exw_abi_version() == 1
+    assert L.exw_abi_version() == 2
     assert _capi.status_string(0) == "EXW_SUCCESS"
     assert _capi.status_string(1) == "EXW_ERROR_INVALID_VALUE"
     assert _capi.status_string(2) == "EXW_ERROR_UNSUPPORTED"
@@ -125,11 +125,12 @@ def test_backward_rejects(kwargs, status, needle):
 
 
 def fwd_rec(src=FAKE, dtype=0, n=1, c=3, h=8, w=8, mv=FAKE + (1 << 30), phases=None, k=1,
-            out=FAKE + (2 << 30), mask=None, count=None, ws=FAKE + (6 << 30), ws_bytes=1 << 30):
+            out=FAKE + (2 << 30), mask=None, count=None, stats=None, ws=FAKE + (6 << 30),
+            ws_bytes=1 << 30):
     if phases is None:
         phases = _phases(1.0)
     return _capi.lib().exw_warp_forward_batched_record(src, dtype, n, c, h, w, mv, phases, k, out,
-                                                       mask, count, ws, ws_bytes, None)
+                                                       mask, count, stats, ws, ws_bytes, None)
 
 
 def bwd_rec(**kwargs):
@@ -154,6 +155,10 @@ def bwd_rec(**kwargs):
     (dict(ws=FAKE + (2 << 30)), INVALID, "overlaps output workspace"),
     (dict(ws=FAKE), INVALID, "workspace overlaps input src"),
     (dict(mask=FAKE + (6 << 30) + 64), INVALID, "mask overlaps output workspace"),
+    (dict(stats=FAKE + (7 << 30) + 4), INVALID, "motion_stats is not 8-byte aligned"),
+    (dict(stats=FAKE + (6 << 30) + 256), INVALID, "workspace overlaps output motion_stats"),
+    (dict(stats=FAKE + 8), INVALID, "motion_stats overlaps input src"),
+    (dict(stats=FAKE + (7 << 30), h=0), INVALID, "no variance"),
 ])
 def test_recording_forward_rejects(kwargs, status, needle):
     st = fwd_rec(**kwargs)
@@ -195,11 +200,16 @@ def test_empty_batches_and_no_requested_gradient_are_no_ops():
 def test_workspace_size():
     L = _capi.lib()
     # per 64-pixel row segment a 16 B tap box and 16 B of tap offsets; 8 B per
-    # frame; float32 accumulator for 16-bit storage
+    # frame; 2 x 24 B of motion-statistics partials per 128 x 4 tile (at least
+    # one per 2048 pixels, at most 256, per frame), 2 x 8 x 24 B of fold slots
+    # and 2 x 4 B of counters per frame; float32 accumulator for 16-bit storage
     def expect(dtype, n, c, h, w):
         boxes = 32 * n * h * ((w + 63) // 64)
         info = (boxes + 255) // 256 * 256
-        accum = (info + 8 * n + 255) // 256 * 256
+        stats = (info + 8 * n + 255) // 256 * 256
+        tiles = ((w + 127) // 128) * ((h + 3) // 4)
+        parts = max(tiles, min(256, (h * w + 2047) // 2048))
+        accum = (stats + 48 * n * parts + 384 * n + 8 * n + 255) // 256 * 256
         return accum + (0 if dtype == 0 else 4 * n * c * h * w)
     for args in [(0, 2, 3, 4, 5), (1, 2, 3, 4, 5), (2, 8, 12, 1440, 2560), (0, 8, 4, 1080, 1920)]:
         assert L.exw_warp_backward_workspace_bytes(*args) == expect(*args), args

@@ -113,3 +113,96 @@ def test_stats_empty_batch_and_binding_checks():
     with pytest.raises(ValueError):
         exw.exw_motion_stats(torch.zeros((1, 2, 4, 4), device=dev),
                              torch.empty((1, 4), device=dev, dtype=torch.float32))
+
+
+# ------------------------------------------ statistics from the recording forward
+
+def record_stats(mv: np.ndarray, c: int, dev, dtype=torch.float32, phases=(0.25, 0.75)):
+    """The recording forward with motion_stats: (stats, out, ws, plain out, plain ws)."""
+    n, _, h, w = mv.shape
+    src = torch.from_numpy(np.random.default_rng(h + w + c).random((n, c, h, w),
+                                                                    dtype=np.float32)).to(dev).to(dtype)
+    m = torch.from_numpy(np.ascontiguousarray(mv, dtype=np.float32)).to(dev)
+    k = len(phases)
+    nbytes = exw.exw_warp_backward_workspace_bytes(dtype, n, c, h, w)
+    outs, wss = [], []
+    stats = torch.full((n, 4), float("nan"), dtype=torch.float64, device=dev)
+    for with_stats in (True, False):
+        out = torch.empty((n, k, c, h, w), dtype=dtype, device=dev)
+        ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        exw.exw_warp_forward_batched_record(src, m, phases, out, ws,
+                                            motion_stats=stats if with_stats else None)
+        outs.append(out)
+        wss.append(ws)
+    torch.cuda.synchronize()
+    return stats.cpu().numpy(), outs, wss
+
+
+def footprint_bytes(ws, n, h, w):
+    seg = 32 * n * h * ((w + 63) // 64)
+    info = (seg + 255) // 256 * 256
+    host = ws.cpu().numpy()
+    return np.concatenate([host[:seg], host[info:info + 8 * n]])
+
+
+@pytest.mark.parametrize("index", sorted(SMALL))
+def test_recording_forward_stats_match_oracle(index):
+    """The statistics the recording forward folds from its own motion read
+    equal the oracle's within the statistics pass's tolerances, and asking for
+    them changes neither the forward's outputs nor its footprint records."""
+    dev = need_gpu()
+    d = make_config(index, **SMALL[index])
+    mv = d["mv"]
+    n, _, h, w = mv.shape
+    c = d["src"].shape[1]
+    announce("recording forward statistics", index, mv.shape, c)
+    got, outs, wss = record_stats(mv, c, dev)
+    assert_stats(got, mv, f"recording forward, workload {index}")
+    assert torch.equal(outs[0], outs[1])
+    assert np.array_equal(footprint_bytes(wss[0], n, h, w), footprint_bytes(wss[1], n, h, w))
+
+
+@pytest.mark.parametrize("c,shape", [(4, (1, 1, 1)), (4, (3, 1, 7)), (3, (2, 5, 129)),
+                                     (1, (1, 2048, 2)), (12, (1, 7, 300)), (4, (2, 45, 46)),
+                                     (4, (1, 517, 1031)),
+                                     (2, (2, 33, 70)),    # plain forward + statistics pass
+                                     (3, (2, 40, 1))])    # width 1: plain forward
+def test_recording_forward_stats_shapes(c, shape):
+    dev = need_gpu()
+    n, h, w = shape
+    mv = np.random.default_rng(h * 5 + w).normal(1.5, 3.0, (n, 2, h, w)).astype(np.float32)
+    announce("recording forward statistics", c, shape)
+    got, outs, _ = record_stats(mv, c, dev)
+    assert_stats(got, mv, f"recording forward c={c} {shape}")
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_recording_forward_stats_large_mean_constant_and_nonfinite():
+    dev = need_gpu()
+    rng = np.random.default_rng(12)
+    # a mean large against the spread (no cancellation), a constant frame
+    mv = np.empty((4, 2, 37, 301), np.float32)
+    mv[0] = 1.0e4 + rng.normal(0.0, 0.01, (2, 37, 301))
+    mv[1] = -2.5
+    mv[2] = rng.normal(0.0, 1.0, (2, 37, 301))
+    mv[2, 0, 17, 200] = np.nan
+    mv[2, 1, 3, 3] = np.inf
+    # one outlier far from the first tile, tiny spread about a large mean
+    mv[3, 0] = 0.0
+    mv[3, 0, 30, 250] = 1.0e6
+    mv[3, 1] = 5.0e3 + rng.normal(0.0, 1.0e-3, (37, 301))
+    announce("recording forward statistics: large mean, constant, outlier, non-finite")
+    got, _, _ = record_stats(mv, 4, dev, dtype=torch.float16)
+    finite = [0, 1, 3]
+    assert_stats(got[finite], mv[finite], "large mean / constant / outlier")
+    assert got[1, 1] == 0.0 and got[1, 3] == 0.0 and got[1, 0] == -2.5
+    assert not np.isfinite(got[2, 0]) and not np.isfinite(got[2, 1])
+    assert not np.isfinite(got[2, 2]) and not np.isfinite(got[2, 3])
+
+
+def test_recording_forward_stats_full_size():
+    dev = need_gpu()
+    d = make_config(2)
+    announce("recording forward statistics, full size", d["mv"].shape)
+    got, _, _ = record_stats(d["mv"], 4, dev, phases=(0.25, 0.5, 0.75))
+    assert_stats(got, d["mv"], "recording forward, workload 2 full size")
