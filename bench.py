@@ -15,8 +15,10 @@ not served from the previous step's caches.
 Prints one JSON line. ``value`` = output pixels (N*K*H*W) per second of a
 forward+backward step, in Mpix/s. Beside it: the other workloads (4K, 16-bit
 storage, random motion, G-buffers), the measured HBM ceilings (hand-written
-copy, read and write streams), the frame quality of the predicted frames
-against the scene's analytic frames, and the CPU leg: the float64 C oracle
+copy, read and write streams), the motion statistics (their own pass, and
+folded by the recording forward), the EMD features of the G-buffers, the
+frame quality of the predicted frames against the scene's analytic frames,
+and the CPU leg: the float64 C oracle
 timed on the host (one thread and the process's CPU share) and, from the same
 oracle, each workload's measured error on its first frame.
 """
@@ -347,6 +349,52 @@ class Workload:
         self.torch.cuda.empty_cache()
 
 
+def buffer_emd_line(dev, reps=20):
+    """The EMD features of the G-buffer workload (4 x 1440p): world normals
+    (3 channels, bfloat16 storage, 256 bins on [-1, 1]) and world positions
+    (3 channels, float32, 1024 bins on [-64, 128]) of frames 1..3 against
+    frames 0..2. Algorithmic bytes: one read of both buffers."""
+    import numpy as np
+    import torch
+    import paper_2307_12607_amd as exw
+    from synth import make_config, world_position
+
+    d = make_config(5)
+    g = d["src"]
+    pos = world_position(g[:, 3], d["info"]["pan"])
+    bufs = (("normals", torch.from_numpy(np.ascontiguousarray(g[:, 4:7])).to(dev).to(torch.bfloat16),
+             -1.0, 1.0, 256),
+            ("positions", torch.from_numpy(pos).to(dev), -64.0, 128.0, 1024))
+    del d, g, pos
+    out = {}
+    for name, buf, lo, hi, bins in bufs:
+        cur, prev = buf[1:], buf[:-1]
+        n, c, h, w = cur.shape
+        emd = torch.empty((n, c), dtype=torch.float64, device=dev)
+        ws = torch.empty(exw.exw_buffer_emd_workspace_bytes(n, c, bins), dtype=torch.uint8,
+                         device=dev)
+        for _ in range(3):
+            exw.exw_buffer_emd(cur, prev, lo, hi, bins, emd, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            exw.exw_buffer_emd(cur, prev, lo, hi, bins, emd, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        nbytes = 2 * cur.numel() * cur.element_size()
+        out[name] = {"workload": f"config5: EMD of {n} frames {w}x{h} C={c} "
+                                 f"{str(cur.dtype).replace('torch.', '')}, {bins} bins",
+                     "us": round(us, 2), "alg_bytes": nbytes,
+                     "gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
+                     "hbm_frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "emd_sum_frame1": round(float(emd[0].sum()), 6)}
+        del cur, prev, buf, emd, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def stream_ceilings(dev, nbytes=1 << 30, reps=10):
     """GB/s of the library's plain HBM streams on 1 GiB buffers: a copy (read +
     write counted), a read-only and a write-only sweep."""
@@ -531,6 +579,7 @@ def main():
                              "bwd_hbm_frac": round(vr["bwd_gbs"] / HBM_PEAK_GBS, 4)})
             wl.free()
 
+    emd_line = None if args.no_variants else buffer_emd_line(dev)
     ceilings = stream_ceilings(dev)
     cpu = None
     errors = None
@@ -575,6 +624,7 @@ def main():
                                            "fwd_bwd_mpix_s": round(alone["mpix_s"], 1)}},
         "variants": variants,
         "motion_stats": stats_line,
+        "buffer_emd": emd_line,
         "frame_quality": quality_line,
         "warp_chain": chain_line,
     }

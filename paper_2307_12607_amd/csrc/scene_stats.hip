@@ -4,13 +4,17 @@
 // Table IV: the motion variance is the feature that reveals dynamic objects).
 //
 // The motion planes are streamed once (8 bytes per pixel, HBM bound). Each
-// thread loads kChunk values per component with coalesced loads, forms the
-// chunk's mean and sum of squared deviations in float64 (two passes over
-// registers), and folds chunks, lanes, wavefronts and finally the partials
-// of all workgroups of a frame together with the pairwise update for
-// (count, mean, M2) (Chan, Golub and LeVeque). Every fold is in a fixed order,
-// so results are reproducible, and no step forms E[x^2] - E[x]^2, which
-// cancels when the mean is large against the spread.
+// thread loads kChunk values per component with coalesced loads and sums, in
+// float64, the differences of its values from its first one and their
+// squares (differences and squares of float32 values are exact in float64):
+// additions only, no division in the loop. At the end each thread forms its
+// (count, mean, M2); the lanes of a wavefront are combined two-pass (the
+// wavefront's mean first, then M2 = sum (M2_i + n_i (mean_i - mean)^2), every
+// term non-negative), and wavefronts and then the partials of all workgroups
+// of a frame with the pairwise update for (count, mean, M2) (Chan, Golub and
+// LeVeque). Every fold is in a fixed order, so results are reproducible, and
+// no step forms E[x^2] - E[x]^2 over more than one thread's values, so a mean
+// that is large against the spread does not cancel.
 #include <mutex>
 
 #include "launch.h"
@@ -24,19 +28,13 @@ constexpr int kChunk = 8;                          // values per thread, per com
 constexpr int kSpan = kStatThreads * kChunk;       // pixels per workgroup pass
 constexpr int kMaxParts = 256;                     // workgroups per frame, at most
 
-__device__ __forceinline__ Moments chunk_moments(const float (&x)[kChunk], int count) {
-    if (count <= 0) return Moments{0.0, 0.0, 0.0};
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) s += j < count ? static_cast<double>(x[j]) : 0.0;
-    const double mean = s / count;
-    double m2 = 0.0;
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-        const double d = static_cast<double>(x[j]) - mean;
-        m2 += j < count ? d * d : 0.0;
-    }
-    return Moments{static_cast<double>(count), mean, m2};
+// The lanes' (count, mean, M2) combined two-pass; the result in every lane.
+__device__ __forceinline__ Moments wave_combine(double n, double mean, double m2, double total) {
+    if (total == 0.0) return Moments{0.0, 0.0, 0.0};  // (wave-uniform)
+    const double mu = wave_sum(n * mean) / total;
+    const double d = mean - mu;
+    // (a lane without values adds 0 * d * d: nothing while the mean is finite)
+    return Moments{total, mu, wave_sum(m2 + n * d * d)};
 }
 
 // grid = n * parts workgroups; workgroup (frame, part) covers passes part,
@@ -48,9 +46,8 @@ __global__ __launch_bounds__(kStatThreads) void motion_moments_kernel(const floa
     const int part = blockIdx.x % parts;
     const float *pu = mv + 2 * static_cast<int64_t>(frame) * hw;
     const float *pv = pu + hw;
-    Moments mu{0.0, 0.0, 0.0}, mvv{0.0, 0.0, 0.0};
     const int64_t stride = static_cast<int64_t>(parts) * kSpan;
-    // The next chunk is loaded while the current one is folded.
+    // The next chunk is loaded while the current one is summed.
     float xu[kChunk], xv[kChunk];
     auto load = [&](int64_t base, float (&u)[kChunk], float (&v)[kChunk]) {
 #pragma unroll
@@ -63,22 +60,43 @@ __global__ __launch_bounds__(kStatThreads) void motion_moments_kernel(const floa
     };
     int64_t base = static_cast<int64_t>(part) * kSpan;
     if (base < hw) load(base, xu, xv);
+    // the shift: the thread's first value (unused when it has none)
+    const double ku = xu[0], kv = xv[0];
+    double s1u = 0.0, s2u = 0.0, s1v = 0.0, s2v = 0.0;
+    int count = 0;
     for (; base < hw; base += stride) {
         float nu[kChunk], nv[kChunk];
         if (base + stride < hw) load(base + stride, nu, nv);
         // in-range values are a prefix of the chunk (j increases with i)
         const int64_t left = (hw - base - threadIdx.x + kStatThreads - 1) / kStatThreads;
-        const int count = static_cast<int>(left < kChunk ? left : kChunk);
-        mu = fold(mu, chunk_moments(xu, count));
-        mvv = fold(mvv, chunk_moments(xv, count));
+        const int c = static_cast<int>(left < kChunk ? left : kChunk);
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            const double du = j < c ? static_cast<double>(xu[j]) - ku : 0.0;
+            const double dv = j < c ? static_cast<double>(xv[j]) - kv : 0.0;
+            s1u += du;
+            s2u = fma(du, du, s2u);
+            s1v += dv;
+            s2v = fma(dv, dv, s2v);
+        }
+        count += c;
 #pragma unroll
         for (int j = 0; j < kChunk; ++j) {
             xu[j] = nu[j];
             xv[j] = nv[j];
         }
     }
-    mu = wave_fold(mu);
-    mvv = wave_fold(mvv);
+    const double n = count;
+    double mean_u = 0.0, m2_u = 0.0, mean_v = 0.0, m2_v = 0.0;
+    if (count > 0) {
+        mean_u = ku + s1u / n;
+        m2_u = s2u - s1u * s1u / n;
+        mean_v = kv + s1v / n;
+        m2_v = s2v - s1v * s1v / n;
+    }
+    const double total = wave_sum(n);
+    const Moments mu = wave_combine(n, mean_u, m2_u, total);
+    const Moments mvv = wave_combine(n, mean_v, m2_v, total);
     const int wave = threadIdx.x / 64;
     if (__lane_id() == 0) {
         lds[0][wave] = mu;
