@@ -54,6 +54,9 @@ def parse():
                    help="skip the CPU leg (oracle timing and the error figures)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 1 GiB device copy first (for counter scaling)")
+    p.add_argument("--only-step", action="store_true",
+                   help="time the step alone: no statistics, EMD, quality, chain or ceiling "
+                        "lines (for profiler runs)")
     return p.parse_args()
 
 
@@ -99,30 +102,86 @@ def _elf_section(path, name):
     return None
 
 
-def device_code_sha():
-    """Hash of the built library's device code (its .hip_fatbin section):
-    stored counter readings apply only to these kernels. Comments and host
-    code do not change it."""
-    import paper_2307_12607_amd._capi as capi
-    code = _elf_section(capi.LIB_PATH, ".hip_fatbin")
-    if code is None:
-        return None
-    return hashlib.sha256(code).hexdigest()[:16]
+def code_objects(lib_path):
+    """The gfx950 code objects (ELF images) in a library's .hip_fatbin
+    section, which holds one clang offload bundle per translation unit: a
+    24-byte magic, the entry count, then per entry its offset (from the
+    bundle's start), size, and target triple."""
+    sec = _elf_section(lib_path, ".hip_fatbin") or b""
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    u64 = lambda o: int.from_bytes(sec[o:o + 8], "little")
+    objs = []
+    pos = sec.find(magic)
+    while pos >= 0:
+        off = pos + len(magic) + 8
+        for _ in range(u64(pos + len(magic))):
+            e_off, e_size, t_size = u64(off), u64(off + 8), u64(off + 16)
+            triple = sec[off + 24:off + 24 + t_size].decode(errors="replace")
+            off += 24 + t_size
+            if "gfx950" in triple and e_size:
+                objs.append(sec[pos + e_off:pos + e_off + e_size])
+        pos = sec.find(magic, off)
+    return objs
 
 
-def load_traffic(kernel, workload):
-    """HBM bytes per launch from stored rocprofv3 counter runs, if they were
-    taken on the current kernels (same device code); else None."""
+def elf_symbols(data):
+    """{symbol name: bytes} of the sized symbols of an ELF64 image (kernel
+    code in .text, kernel descriptors `<name>.kd`)."""
+    u16 = lambda o: int.from_bytes(data[o:o + 2], "little")
+    u32 = lambda o: int.from_bytes(data[o:o + 4], "little")
+    u64 = lambda o: int.from_bytes(data[o:o + 8], "little")
+    shoff, shentsize, shnum = u64(0x28), u16(0x3A), u16(0x3C)
+    secs = []
+    for i in range(shnum):
+        b = shoff + i * shentsize
+        secs.append({"type": u32(b + 4), "addr": u64(b + 0x10), "offset": u64(b + 0x18),
+                     "size": u64(b + 0x20), "link": u32(b + 0x28)})
+    out = {}
+    for sec in secs:
+        if sec["type"] != 2:  # SHT_SYMTAB
+            continue
+        strtab = secs[sec["link"]]["offset"]
+        for e in range(sec["offset"], sec["offset"] + sec["size"], 24):
+            name_off, shndx, value, size = u32(e), u16(e + 6), u64(e + 8), u64(e + 16)
+            if size == 0 or shndx == 0 or shndx >= len(secs):
+                continue
+            end = data.index(b"\0", strtab + name_off)
+            name = data[strtab + name_off:end].decode(errors="replace")
+            tgt = secs[shndx]
+            start = tgt["offset"] + (value - tgt["addr"])
+            out[name] = data[start:start + size]
+    return out
+
+
+def kernel_code_sha(names, lib_path=None):
+    """Hash of the named kernels' machine code and descriptors in the built
+    library (None if one is missing): stored counter readings apply only
+    while the kernels they were taken on are unchanged. Other kernels,
+    comments and host code do not change it."""
+    if lib_path is None:
+        import paper_2307_12607_amd._capi as capi
+        lib_path = capi.LIB_PATH
+    syms = {}
+    for obj in code_objects(lib_path):
+        syms.update(elf_symbols(obj))
+    h = hashlib.sha256()
+    for name in sorted(names):
+        if name not in syms:
+            return None
+        h.update(name.encode() + syms[name] + syms.get(name + ".kd", b""))
+    return h.hexdigest()[:16]
+
+
+def load_traffic(call, workload):
+    """HBM bytes per call from stored rocprofv3 counter runs, if they were
+    taken on the kernels the library now holds; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    sha = device_code_sha()
-    if sha is None or rec.get("device_code_sha") != sha:
-        return None
-    entry = rec.get("kernels", {}).get(f"{kernel}|{workload}")
-    if not entry:
+    entry = rec.get("calls", {}).get(f"{call}|{workload}")
+    if not entry or kernel_code_sha(entry["kernels"]) != entry.get("code_sha"):
         return None
     return entry.get("hbm_bytes_per_launch")
 
@@ -551,9 +610,9 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     wl_name = main_wl.name()
     traffic = load_traffic(dominant, wl_name)
-    stats_line = main_wl.run_motion_stats()
+    stats_line = None if args.only_step else main_wl.run_motion_stats()
     quality_line = chain_line = None
-    if main_wl.truth is not None:
+    if main_wl.truth is not None and not args.only_step:
         quality_line, chain_line = main_wl.run_quality_and_chain()
         chain_line["direct_fwd_phases_us"] = round(r["fwd_ms"] * 1e3, 1)
     main_wl.free()
@@ -579,8 +638,8 @@ def main():
                              "bwd_hbm_frac": round(vr["bwd_gbs"] / HBM_PEAK_GBS, 4)})
             wl.free()
 
-    emd_line = None if args.no_variants else buffer_emd_line(dev)
-    ceilings = stream_ceilings(dev)
+    emd_line = None if args.no_variants or args.only_step else buffer_emd_line(dev)
+    ceilings = None if args.only_step else stream_ceilings(dev)
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
@@ -607,7 +666,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "frac_of_measured_copy": round(achieved / ceilings["copy_gbs"], 4)},
+                     "frac_of_measured_copy": (round(achieved / ceilings["copy_gbs"], 4)
+                                               if ceilings else None)},
         "cpu_baseline": cpu,
         "errors": errors,
         "breakdown": {"fwd_ms": round(r["fwd_ms"], 4), "bwd_ms": round(r["bwd_ms"], 4),

@@ -13,7 +13,11 @@
 // Pass 1: workgroups own a contiguous run of one plane of both buffers,
 // count into LDS histograms (integer LDS atomics; both buffers' counts side
 // by side) and add their non-zero bins to the plane's global counters with
-// one integer atomic each. Pass 2: one workgroup per plane scans the count
+// one integer atomic each. Smooth buffers put many lanes of a wavefront in
+// one bin, and atomics on one address serialise: the workgroup keeps up to
+// four copies of its histograms, lane l counting into copy l mod copies (the
+// copies one word apart, so one bin of different copies falls in different
+// banks), and adds the copies up at the end. Pass 2: one workgroup per plane scans the count
 // differences in 64-bit integers and sums their magnitudes exactly; the
 // result is that exact sum / (H*W) * width in float64. Integer counts make
 // every result independent of the order of the atomics.
@@ -31,6 +35,8 @@ constexpr int kEmdUnroll = 4;                          // loads in flight per th
 constexpr int64_t kEmdRun = 16384;                     // values of a plane per workgroup, at least
 constexpr int kEmdMaxParts = 128;                      // workgroups per plane, at most
 
+constexpr int kEmdLdsWords = 8200;                     // LDS words for the copies, at most (~32 KB)
+
 struct EmdArgs {
     const void *cur, *prev;
     int64_t hw;
@@ -38,6 +44,8 @@ struct EmdArgs {
     int64_t run;       // values per workgroup (the last one may hold fewer)
     double lo, scale;  // bin = floor((v - lo) * scale), clamped
     int bins;
+    int copies;        // LDS copies of the two histograms (1, 2 or 4)
+    int stride;        // words from one copy to the next: 2 * bins + 1
     uint32_t *counts;  // [planes][2][bins]
 };
 
@@ -49,11 +57,12 @@ __device__ __forceinline__ int bin_of(float v, double lo, double scale, int bins
 
 template <typename T>
 __global__ __launch_bounds__(kEmdThreads) void emd_hist_kernel(EmdArgs a) {
-    extern __shared__ uint32_t hist[];  // [2][bins]
+    extern __shared__ uint32_t lds[];  // [copies][stride]: [2][bins] and a pad word each
     const int plane = static_cast<int>(blockIdx.x) / a.parts;
     const int part = static_cast<int>(blockIdx.x) - plane * a.parts;
-    for (int i = threadIdx.x; i < 2 * a.bins; i += kEmdThreads) hist[i] = 0u;
+    for (int i = threadIdx.x; i < a.copies * a.stride; i += kEmdThreads) lds[i] = 0u;
     __syncthreads();
+    uint32_t *hist = lds + (static_cast<int>(threadIdx.x) & (a.copies - 1)) * a.stride;
     const T *pa = static_cast<const T *>(a.cur) + static_cast<int64_t>(plane) * a.hw;
     const T *pb = static_cast<const T *>(a.prev) + static_cast<int64_t>(plane) * a.hw;
     const int64_t begin = static_cast<int64_t>(part) * a.run;
@@ -76,8 +85,11 @@ __global__ __launch_bounds__(kEmdThreads) void emd_hist_kernel(EmdArgs a) {
     }
     __syncthreads();
     uint32_t *g = a.counts + static_cast<int64_t>(plane) * 2 * a.bins;
-    for (int i = threadIdx.x; i < 2 * a.bins; i += kEmdThreads)
-        if (hist[i] != 0u) atomicAdd(&g[i], hist[i]);
+    for (int i = threadIdx.x; i < 2 * a.bins; i += kEmdThreads) {
+        uint32_t t = lds[i];
+        for (int k = 1; k < a.copies; ++k) t += lds[k * a.stride + i];
+        if (t != 0u) atomicAdd(&g[i], t);
+    }
 }
 
 // One workgroup per plane: S = sum_i |CA_i - CB_i| over the cumulative counts,
@@ -143,9 +155,12 @@ hipError_t launch_buffer_emd(int dtype, const void *cur, const void *prev, int n
     a.lo = lo;
     a.scale = static_cast<double>(bins) / (hi - lo);
     a.bins = bins;
+    a.stride = 2 * bins + 1;
+    a.copies = 4;
+    while (a.copies > 1 && a.copies * a.stride > kEmdLdsWords) a.copies /= 2;
     a.counts = counts;
     const dim3 grid(static_cast<unsigned>(planes * a.parts));
-    const size_t lds = sizeof(uint32_t) * 2 * bins;
+    const size_t lds = sizeof(uint32_t) * a.copies * a.stride;
     switch (dtype) {
     case 0: hipLaunchKernelGGL(emd_hist_kernel<float>, grid, dim3(kEmdThreads), lds, stream, a); break;
     case 1: hipLaunchKernelGGL(emd_hist_kernel<_Float16>, grid, dim3(kEmdThreads), lds, stream, a); break;

@@ -460,6 +460,21 @@ __device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &
     return true;  // no invalid pixel: the zeroed counts stay as they are
 }
 
+// pair_uniform with the lane's motion loaded here (the kernels without
+// statistics: the loads stay next to their first use).
+template <typename T, int CT, int KT>
+__device__ __forceinline__ bool pair_uniform_load(const FwdArgs<T> &a, const SegPos &g,
+                                                  int (&orx)[KT], int (&ory)[KT]) {
+    const int64_t hw = static_cast<int64_t>(a.h) * a.w;
+    const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
+    const uint32_t p = static_cast<uint32_t>(g.y) * static_cast<uint32_t>(a.w) +
+                       static_cast<uint32_t>(g.sx0 + 2 * static_cast<int>(threadIdx.x));
+    float u0, u1, v0, v1;
+    load_pair(at(mu, p), u0, u1);
+    load_pair(at(mu + hw, p), v0, v1);
+    return pair_uniform<T, CT, KT>(a, g, u0, u1, v0, v1, orx, ory, [] {});
+}
+
 // Footprint records of the wavefront's two 64-pixel segments after the
 // two-pixel path: every pixel valid with the offsets (rx, ry) in every phase,
 // so the boxes follow from the offsets (what segment_footprint gives).
@@ -619,7 +634,6 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
         }
     }
     const SegPos g = decode_segment(a.tiles_x, a.tiles_y);
-    const bool full = g.y < a.h && g.sx0 + kSegPair <= a.w;  // wave-uniform
     if constexpr (STATS) {
         // the motion of the wavefront's pixels 2j, 2j+1 (lane j), for the
         // statistics and the two-pixel path alike
@@ -635,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
                             static_cast<uint32_t>(g.sx0);
         const float su = *at(mu, p0), sv = *at(mu + hw, p0);
         float u0 = 0.0f, u1 = 0.0f, v0 = 0.0f, v1 = 0.0f;
-        if (full) {
+        if (g.y < a.h && g.sx0 + kSegPair <= a.w) {  // wave-uniform (see below)
             load_pair(at(mu, p), u0, u1);
             load_pair(at(mu + hw, p), v0, v1);
         } else {
@@ -647,7 +661,7 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
         if constexpr (2 * CT * KT <= kTileW) {
             int rx[KT], ry[KT];
             // (the sums are formed while the first gathers are in flight)
-            if (a.frame_32bit && full &&
+            if (a.frame_32bit && g.y < a.h && g.sx0 + kSegPair <= a.w &&
                 pair_uniform<T, CT, KT>(a, g, u0, u1, v0, v1, rx, ry, sums)) {
                 record_pair<T, KT>(a, g, rx, ry);
                 done = true;
@@ -664,18 +678,12 @@ __global__ __launch_bounds__(kThreads) void warp_forward_kernel(FwdArgs<T> a) {
         return;
     } else if constexpr (2 * CT * KT <= kTileW) {
         int rx[KT], ry[KT];
-        if (a.frame_32bit && full) {
-            const int64_t hw = static_cast<int64_t>(a.h) * a.w;
-            const float *mu = a.mv + 2 * static_cast<int64_t>(g.in) * hw;
-            const uint32_t p = static_cast<uint32_t>(g.y) * static_cast<uint32_t>(a.w) +
-                               static_cast<uint32_t>(g.sx0 + 2 * static_cast<int>(threadIdx.x));
-            float u0, u1, v0, v1;
-            load_pair(at(mu, p), u0, u1);
-            load_pair(at(mu + hw, p), v0, v1);
-            if (pair_uniform<T, CT, KT>(a, g, u0, u1, v0, v1, rx, ry, [] {})) {
-                if constexpr (REC) record_pair<T, KT>(a, g, rx, ry);
-                return;
-            }
+        // (the condition stays in this form: a flag computed ahead of the
+        // branch raised this kernel from 65 to 89 VGPRs, two waves per SIMD)
+        if (a.frame_32bit && g.y < a.h && g.sx0 + kSegPair <= a.w &&  // wave-uniform
+            pair_uniform_load<T, CT, KT>(a, g, rx, ry)) {
+            if constexpr (REC) record_pair<T, KT>(a, g, rx, ry);
+            return;
         }
     }
 #pragma unroll 1

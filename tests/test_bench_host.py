@@ -1,6 +1,6 @@
 """Host-side logic of bench.py (no GPU): the one-GPU contract, the algorithmic
-byte counts the roofline figure is built on, and the device-code key of the
-traffic counters."""
+byte counts the roofline figure is built on, and the per-kernel code key of
+the traffic counters (with the profile summariser's kernel names)."""
 
 import os
 import subprocess
@@ -35,9 +35,48 @@ def test_algorithmic_bytes_of_the_main_workload():
     assert b16 == px * k * c * 2 + px * (c * 2 + 8 + c * 2 + 8)
 
 
-def test_device_code_key_and_traffic_lookup():
-    sha = bench.device_code_sha()
-    assert sha is None or (len(sha) == 16 and all(ch in "0123456789abcdef" for ch in sha))
+def _lib():
+    import paper_2307_12607_amd._capi as capi
+    return capi.LIB_PATH
+
+
+def test_code_objects_and_kernel_symbols_of_the_library():
+    objs = bench.code_objects(_lib())
+    assert len(objs) >= 5  # one per translation unit with device code
+    syms = {}
+    for o in objs:
+        assert o[:4] == b"\x7fELF"
+        syms.update(bench.elf_symbols(o))
+    tiles = [n for n in syms if "adjoint_tiles_kernelIfLi4ELi3E" in n and not n.endswith(".kd")]
+    assert len(tiles) == 1 and tiles[0] + ".kd" in syms
+    assert len(syms[tiles[0] + ".kd"]) == 64  # an AMDGPU kernel descriptor
+
+
+def test_kernel_code_key_and_traffic_lookup():
+    syms = {}
+    for o in bench.code_objects(_lib()):
+        syms.update(bench.elf_symbols(o))
+    names = sorted(n for n in syms if ("adjoint_tiles_kernelIfLi4ELi3E" in n
+                                       or "adjoint_far_kernelIfLi4ELi3E" in n)
+                   and not n.endswith(".kd"))
+    sha = bench.kernel_code_sha(names, _lib())
+    assert len(sha) == 16 and all(ch in "0123456789abcdef" for ch in sha)
+    assert bench.kernel_code_sha(list(reversed(names)), _lib()) == sha  # order-free
+    assert bench.kernel_code_sha(names[:1], _lib()) != sha
+    assert bench.kernel_code_sha(names + ["_Z_no_such_kernel"], _lib()) is None
     t = bench.load_traffic("warp_backward", "config2: 8x1920x1080 C=4 K=3 f32")
     assert t is None or (isinstance(t, int) and t > 0)
-    assert bench.load_traffic("no_such_kernel", "no workload") is None
+    assert bench.load_traffic("no_such_call", "no workload") is None
+
+
+def test_profile_names_match_symbols():
+    import bench_traffic as bt
+    assert bt.key("void exw::(anonymous namespace)::adjoint_tiles_kernel<float, 4, 3>"
+                  "(exw::(anonymous namespace)::BwdArgs<float>)") == "exw::adjoint_tiles_kernel<float, 4, 3>"
+    # the profiler leaves the 16-bit instantiations mangled; both sides read them alike
+    m = "_ZN3exw12_GLOBAL__N_120adjoint_tiles_kernelIDF16bLi12ELi1EEEvNS0_7BwdArgsIT_EE"
+    assert bt.demangle([m]) == ["exw::adjoint_tiles_kernel<__bf16, 12, 1>"]
+    keys = bt.symbols_by_key()
+    assert keys["exw::adjoint_tiles_kernel<__bf16, 12, 1>"] == m
+    assert "exw::warp_forward_kernel<half, 4, 3, true, false>" in keys
+    assert "exw::stream_copy_kernel" in keys
