@@ -48,6 +48,9 @@ def test_edge_cases():
         (2, 3, 5, 7, -1.0, 1.0, 4096),
         (1, 2, 33, 65, -0.5, 0.25, 3),
         (3, 1, 129, 131, -2.0, 2.0, 100),
+        (2, 2, 64, 300, -3.0, 3.0, 1500),   # two LDS copies of the histograms
+        (1, 3, 50, 77, -1.0, 1.0, 2048),    # two copies, the largest such bin count
+        (1, 1, 70, 90, -1.0, 1.0, 2049),    # one copy
     ]
     for n, c, h, w, lo, hi, bins in cases:
         announce("buffer EMD edge", n, c, h, w, bins)
