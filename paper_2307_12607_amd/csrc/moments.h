@@ -2,9 +2,12 @@
 // their pairwise combination (Chan, Golub and LeVeque), used by the motion
 // statistics (paper §IV-C, Eq. 1: Var_x(F_mv), Var_y(F_mv) of E_t): by the
 // statistics pass and by the recording forward, which folds the motion it
-// reads anyway. Every fold is in a fixed order, so results are reproducible,
-// and no step forms E[x^2] - E[x]^2, which cancels when the mean is large
-// against the spread.
+// reads anyway. Every fold is in a fixed order, so results are reproducible.
+// Sums of squares are formed only about a shift inside a small group of
+// values (one thread's, or one 128 x 4 tile's), which bounds their
+// cancellation by the group's size; everything above a group is combined
+// two-pass or pairwise, never as E[x^2] - E[x]^2 over the frame, which
+// cancels when the mean is large against the spread.
 #pragma once
 
 #include <hip/hip_runtime.h>
