@@ -169,12 +169,16 @@ def pan_rect_sequence(rng: np.random.Generator, n: int, h: int, w: int, *, kind:
     xs = np.arange(w, dtype=np.float64)
     ys = np.arange(h, dtype=np.float64)
 
-    def render(t: float):
-        # the scene at time t (in rendered-frame intervals): image and motion
+    def render(t: float, stencil=None):
+        # the scene at time t (in rendered-frame intervals): image and motion;
+        # with `stencil` [H, W] u8, also the custom stencil (1 where a moving
+        # rectangle is the topmost surface, 0 on the background)
         frame = bg.eval(xs - t * pan[0], ys - t * pan[1])
         motion = np.empty((2, h, w), dtype=np.float32)
         motion[0] = np.float32(pan[0])
         motion[1] = np.float32(pan[1])
+        if stencil is not None:
+            stencil[...] = 0
         for rw, rh, rx, ry, vel, surf in rects:
             left = rx + t * vel[0]
             top = ry + t * vel[1]
@@ -185,14 +189,17 @@ def pan_rect_sequence(rng: np.random.Generator, n: int, h: int, w: int, *, kind:
             frame[:, ya:yb, xa:xb] = surf.eval(xs[xa:xb] - left, ys[ya:yb] - top)
             motion[0, ya:yb, xa:xb] = np.float32(vel[0])
             motion[1, ya:yb, xa:xb] = np.float32(vel[1])
+            if stencil is not None:
+                stencil[ya:yb, xa:xb] = 1
         return frame, motion
 
     frames = np.empty((n, c, h, w), dtype=np.float32)
     mv = np.empty((n, 2, h, w), dtype=np.float32)
+    stencil = np.empty((n, h, w), dtype=np.uint8)
     for i in range(n):
-        frames[i], mv[i] = render(float(i))
+        frames[i], mv[i] = render(float(i), stencil[i])
     info = {"pan": pan.tolist(), "n_rects": n_rects, "vmax": vmax,
-            "velocities": [r[4].tolist() for r in rects]}
+            "velocities": [r[4].tolist() for r in rects], "stencil": stencil}
     if truth_phases is not None:
         # the exact scene between rendered frames: what a perfect predictor shows
         truth = np.empty((n, len(truth_phases), c, h, w), dtype=np.float32)
@@ -252,7 +259,9 @@ def make_config(index: int, *, n: Optional[int] = None, h: Optional[int] = None,
     ``phases`` [K] float32, ``delta`` [N,2,H,W] float32 or None (the motion
     perturbation of the L2 target), ``truth`` [N,K,C,H,W] float32 (the scene
     at times n + phase, pan-and-rectangle workloads with ``with_truth``) or
-    None, plus the spec. The default seed is
+    None, ``stencil`` [N,H,W] uint8 (the custom stencil of the
+    pan-and-rectangle workloads: 1 on moving rectangles, 0 on the
+    background) or None, plus the spec. The default seed is
     ``1000 + index``. At a reduced size rectangle sizes shrink with the frame,
     velocities do not.
     """
@@ -275,8 +284,9 @@ def make_config(index: int, *, n: Optional[int] = None, h: Optional[int] = None,
     if spec.delta_std > 0:
         delta = rng.normal(0.0, spec.delta_std, size=mv.shape).astype(np.float32)
     truth = info.pop("truth", None)
+    stencil = info.pop("stencil", None)
     return {"spec": spec, "src": src, "mv": mv, "phases": np.asarray(spec.phases, np.float32),
-            "delta": delta, "info": info, "truth": truth}
+            "delta": delta, "info": info, "truth": truth, "stencil": stencil}
 
 
 def quantize(x: np.ndarray, dtype: str) -> np.ndarray:
