@@ -412,7 +412,8 @@ def buffer_emd_line(dev, reps=20):
     """The EMD features of the G-buffer workload (4 x 1440p): world normals
     (3 channels, bfloat16 storage, 256 bins on [-1, 1]) and world positions
     (3 channels, float32, 1024 bins on [-64, 128]) of frames 1..3 against
-    frames 0..2. Algorithmic bytes: one read of both buffers."""
+    frames 0..2 (algorithmic bytes: one read of both buffers); and N_D, the
+    number of dynamic objects, of its 4 frames' custom stencil."""
     import numpy as np
     import torch
     import paper_2307_12607_amd as exw
@@ -421,6 +422,7 @@ def buffer_emd_line(dev, reps=20):
     d = make_config(5)
     g = d["src"]
     pos = world_position(g[:, 3], d["info"]["pan"])
+    stencil = torch.from_numpy(d["stencil"]).to(dev)
     bufs = (("normals", torch.from_numpy(np.ascontiguousarray(g[:, 4:7])).to(dev).to(torch.bfloat16),
              -1.0, 1.0, 256),
             ("positions", torch.from_numpy(pos).to(dev), -64.0, 128.0, 1024))
@@ -450,6 +452,26 @@ def buffer_emd_line(dev, reps=20):
                      "hbm_frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                      "emd_sum_frame1": round(float(emd[0].sum()), 6)}
         del cur, prev, buf, emd, ws
+    # N_D of the same frames: connected components of the custom stencil
+    n, h, w = stencil.shape
+    count = torch.empty((n,), dtype=torch.int32, device=dev)
+    ws = torch.empty(exw.exw_dynamic_objects_workspace_bytes(n, h, w), dtype=torch.uint8,
+                     device=dev)
+    for _ in range(3):
+        exw.exw_dynamic_objects(stencil, count, ws, 8)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        exw.exw_dynamic_objects(stencil, count, ws, 8)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    out["dynamic_objects"] = {"workload": f"config5: N_D of {n} frames {w}x{h} (custom stencil, "
+                                          f"8-connectivity)",
+                              "us": round(us, 2), "gpix_s": round(n * h * w / (us * 1e-6) / 1e9, 1),
+                              "n_d": count.cpu().tolist()}
+    del stencil, count, ws
     torch.cuda.empty_cache()
     return out
 

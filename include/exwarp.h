@@ -301,6 +301,35 @@ exw_status exw_buffer_emd(const void *cur, const void *prev, exw_dtype dtype, in
                           double *emd, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * N_D, the number of dynamic objects (paper §III-D, State Representation:
+ * the custom stencil buffer marks the pixels of dynamic objects, which are
+ * found by clustering it; Table IV; §IV-C, Eq. 1: an entry of E_t). The
+ * paper names no clustering method; here an object is a connected component
+ * of the marked pixels (stencil value non-zero), two marked pixels being
+ * joined when they share an edge (4-connectivity) or an edge or a corner
+ * (8-connectivity). Objects that touch or overlap count once.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace exw_dynamic_objects needs: one int32 label per
+ * pixel (4 * N * H * W). Returns 0 for an empty batch. */
+size_t exw_dynamic_objects_workspace_bytes(int32_t n, int32_t h, int32_t w);
+
+/*
+ * count[n] = number of connected components of the marked pixels of frame n.
+ *   stencil:      [N, H, W] uint8, device (marked = non-zero).
+ *   connectivity: 4 or 8.
+ *   count:        [N] uint32, device, 4-byte aligned; overwritten.
+ *   workspace:    device scratch of at least exw_dynamic_objects_workspace_bytes()
+ *                 bytes, 256-byte aligned.
+ * The count is exact and does not depend on the order in which the GPU
+ * joins pixels. N = 0 does nothing; frames with H = 0 or W = 0 have no
+ * objects (count 0). H * W is at most 2^30.
+ */
+exw_status exw_dynamic_objects(const uint8_t *stencil, int32_t n, int32_t h, int32_t w,
+                               int32_t connectivity, uint32_t *count, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Frame quality.
  *
  * Paper §IV-C1: the reward of the warp/extrapolate decision is the gain in PSNR

@@ -41,6 +41,8 @@ from .binding import (  # noqa: F401
     exw_motion_stats_no_alloc,
     exw_buffer_emd,
     exw_buffer_emd_workspace_bytes,
+    exw_dynamic_objects,
+    exw_dynamic_objects_workspace_bytes,
     exw_warp_forward,
     exw_warp_forward_batched,
     exw_warp_forward_batched_record,
@@ -171,6 +173,19 @@ def buffer_emd(cur: torch.Tensor, prev: torch.Tensor, lo: float, hi: float,
     return emd
 
 
+def dynamic_objects(stencil: torch.Tensor, connectivity: int = 8) -> torch.Tensor:
+    """N_D of every frame: the number of connected components of the marked
+    (non-zero) pixels of the custom stencil ``stencil`` [N,H,W] uint8, as an
+    int32 [N] device tensor."""
+    stencil = stencil.contiguous()
+    n, h, w = stencil.shape
+    count = torch.empty((n,), dtype=torch.int32, device=stencil.device)
+    nbytes = exw_dynamic_objects_workspace_bytes(n, h, w)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=stencil.device)
+    exw_dynamic_objects(stencil, count, ws, connectivity)
+    return count
+
+
 def frame_quality(pred: torch.Tensor, truth: torch.Tensor, peak: float = 1.0) -> torch.Tensor:
     """Per-frame ``(MSE, PSNR, SSIM)`` of ``pred`` against ``truth``, both
     [..., C, H, W] of one dtype, as a float64 [..., 3] device tensor."""
@@ -258,4 +273,5 @@ __all__ = ["ExwError", "warp", "warp_backward", "WarpFunction", "warp_differenti
            "exw_frame_quality_workspace_bytes", "exw_warp_chain", "exw_decision_plan",
            "exw_threshold_policy", "exw_stream_copy", "exw_stream_read", "exw_stream_write",
            "exw_motion_stats_no_alloc", "exw_buffer_emd", "exw_buffer_emd_workspace_bytes",
-           "buffer_emd"]
+           "buffer_emd", "exw_dynamic_objects", "exw_dynamic_objects_workspace_bytes",
+           "dynamic_objects"]

@@ -55,6 +55,8 @@ SIGNATURES = {
     "exw_buffer_emd_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "exw_buffer_emd": (ctypes.c_int, [_p, _p, ctypes.c_int, _i32, _i32, _i32, _i32,
                                       ctypes.c_double, ctypes.c_double, _i32, _p, _p, _sz, _p]),
+    "exw_dynamic_objects_workspace_bytes": (_sz, [_i32, _i32, _i32]),
+    "exw_dynamic_objects": (ctypes.c_int, [_p, _i32, _i32, _i32, _i32, _p, _p, _sz, _p]),
     "exw_stream_copy": (ctypes.c_int, [_p, _p, _sz, _p]),
     "exw_stream_read": (ctypes.c_int, [_p, _sz, _p, _p]),
     "exw_stream_write": (ctypes.c_int, [_p, _sz, _p]),

@@ -262,6 +262,33 @@ def exw_buffer_emd(cur: torch.Tensor, prev: torch.Tensor, lo: float, hi: float, 
     check(st, "exw_buffer_emd")
 
 
+def exw_dynamic_objects_workspace_bytes(n: int, h: int, w: int) -> int:
+    return int(lib().exw_dynamic_objects_workspace_bytes(n, h, w))
+
+
+def exw_dynamic_objects(stencil: torch.Tensor, count: torch.Tensor,
+                        workspace: Optional[torch.Tensor] = None, connectivity: int = 8,
+                        stream=None) -> None:
+    """stencil [N,H,W] uint8 -> count [N] int32 (bit pattern of the C ABI's
+    uint32): the number of connected components of the marked (non-zero)
+    pixels of each frame. ``workspace``: a byte tensor of at least
+    ``exw_dynamic_objects_workspace_bytes`` bytes."""
+    dev = stencil.device
+    _dev(stencil, "stencil", dev)
+    if stencil.dim() != 3:
+        raise ValueError(f"stencil has shape {tuple(stencil.shape)}, expected [N, H, W]")
+    n, h, w = stencil.shape
+    _expect(stencil, "stencil", (n, h, w), torch.uint8, dev)
+    _expect(count, "count", (n,), torch.int32, dev)
+    ws_bytes = 0
+    if workspace is not None:
+        _dev(workspace, "workspace", dev)
+        ws_bytes = workspace.numel() * workspace.element_size()
+    st = lib().exw_dynamic_objects(_ptr(stencil), n, h, w, connectivity, _ptr(count),
+                                   _ptr(workspace), ws_bytes, _stream(dev, stream))
+    check(st, "exw_dynamic_objects")
+
+
 def exw_frame_quality_workspace_bytes(b: int, c: int, h: int, w: int) -> int:
     return int(lib().exw_frame_quality_workspace_bytes(b, c, h, w))
 

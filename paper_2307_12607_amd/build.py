@@ -14,7 +14,8 @@ LIB = os.path.join(PKG, "libexwarp.so")
 SOURCES = [os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "warp_forward.hip"),
            os.path.join(CSRC, "warp_backward.hip"), os.path.join(CSRC, "scene_stats.hip"),
            os.path.join(CSRC, "quality.hip"), os.path.join(CSRC, "schedule.cpp"),
-           os.path.join(CSRC, "stream_ceiling.hip"), os.path.join(CSRC, "buffer_emd.hip")]
+           os.path.join(CSRC, "stream_ceiling.hip"), os.path.join(CSRC, "buffer_emd.hip"),
+           os.path.join(CSRC, "dynamic_objects.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

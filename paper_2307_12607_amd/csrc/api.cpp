@@ -518,6 +518,49 @@ exw_status exw_buffer_emd(const void *cur, const void *prev, exw_dtype dtype, in
                     "buffer EMD launch");
 }
 
+size_t exw_dynamic_objects_workspace_bytes(int32_t n, int32_t h, int32_t w) {
+    if (n <= 0 || h <= 0 || w <= 0) return 0;
+    return exw::dynamic_objects_workspace_bytes(n, h, w);
+}
+
+exw_status exw_dynamic_objects(const uint8_t *stencil, int32_t n, int32_t h, int32_t w,
+                               int32_t connectivity, uint32_t *count, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+    if (n < 0 || h < 0 || w < 0)
+        return fail(EXW_ERROR_INVALID_VALUE, "negative size (n=%d, h=%d, w=%d)", n, h, w);
+    if (connectivity != 4 && connectivity != 8)
+        return fail(EXW_ERROR_INVALID_VALUE, "connectivity %d is not 4 or 8", connectivity);
+    if (n == 0) return succeed();
+    const uint64_t hw = uint64_t(h) * uint64_t(w);
+    if (hw > (uint64_t(1) << 30))
+        return fail(EXW_ERROR_UNSUPPORTED, "h*w = %llu > 2^30", (unsigned long long)hw);
+    const uint64_t px = uint64_t(n) * hw;
+    if (px > kMaxElems)
+        return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu pixels)",
+                    (unsigned long long)px);
+    EXW_TRY(check_ptr("count", count, 4, true));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hw == 0)  // no pixels, no objects
+        return launched(exw::launch_zero_u32(count, n, st), "dynamic objects launch");
+    const uint64_t tiles = uint64_t(n) * ((uint64_t(w) + 31) / 32) * ((uint64_t(h) + 31) / 32);
+    if (tiles >= (uint64_t(1) << 31))
+        return fail(EXW_ERROR_UNSUPPORTED, "too many 32 x 32 tiles (%llu)",
+                    (unsigned long long)tiles);
+    EXW_TRY(check_ptr("stencil", stencil, 1, true));
+    EXW_TRY(check_ptr("workspace", workspace, 256, true));
+    const size_t ws_need = exw::dynamic_objects_workspace_bytes(n, h, w);
+    if (workspace_bytes < ws_need)
+        return fail(EXW_ERROR_INVALID_VALUE, "workspace has %zu bytes, needs %zu",
+                    workspace_bytes, ws_need);
+    const Span ins[] = {span("stencil", stencil, px)};
+    const Span outs[] = {span("count", count, uint64_t(n) * 4u),
+                         span("workspace", workspace, ws_need)};
+    EXW_TRY(check_disjoint(outs, 2, ins, 1));
+    return launched(exw::launch_dynamic_objects(stencil, n, h, w, connectivity, count, workspace,
+                                                st),
+                    "dynamic objects launch");
+}
+
 exw_status exw_warp_chain(const void *src, exw_dtype dtype, int32_t n, int32_t c, int32_t h,
                           int32_t w, const float *mv, float phase, int32_t steps, void *out,
                           uint8_t *mask, uint32_t *invalid_count, void *stream) {

@@ -94,6 +94,13 @@ hipError_t launch_quality(int dtype, const void *pred, const void *truth, int b,
                           int w, double peak, double *quality, void *workspace,
                           hipStream_t stream);
 
+// N_D: connected components of the marked pixels of stencil [N, H, W] (u8,
+// marked = non-zero), 4- or 8-connectivity, into count [N]; the workspace
+// holds one int32 label per pixel.
+size_t dynamic_objects_workspace_bytes(int n, int h, int w);
+hipError_t launch_dynamic_objects(const uint8_t *stencil, int n, int h, int w, int connectivity,
+                                  uint32_t *count, void *workspace, hipStream_t stream);
+
 // Per-frame, per-channel EMD between two buffers [N, C, H, W] (histograms of
 // `bins` bins on [lo, hi]); emd[n][c] in float64.
 size_t buffer_emd_workspace_bytes(int n, int c, int bins);

@@ -69,11 +69,6 @@ struct PixelPos {
 };
 
 
-// v from lane + 1 (0 into lane 63): a DPP wavefront shift.
-__device__ __forceinline__ float shift_down1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
-}
-
 // v from lane + 1, and `last` (a value read back from another lane) into
 // lane 63. Read-backs are taken outside divergent code: inside a branch of
 // lane 63 alone, the compiler may sink the load they read there, and the

@@ -403,3 +403,34 @@ def test_buffer_emd_empty_batch_and_workspace_size():
     assert L.exw_buffer_emd_workspace_bytes(2, 3, 100) == 2 * 3 * 2 * 100 * 4
     assert L.exw_buffer_emd_workspace_bytes(0, 3, 100) == 0
     assert L.exw_buffer_emd_workspace_bytes(1, 3, 4097) == 0
+
+
+def dyn(st=FAKE, n=2, h=40, w=70, conn=8, count=FAKE + (1 << 30), ws=FAKE + (2 << 30),
+        ws_bytes=1 << 20):
+    return _capi.lib().exw_dynamic_objects(st, n, h, w, conn, count, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kwargs,status,needle", [
+    (dict(n=-1), 1, "negative size"),
+    (dict(conn=6), 1, "connectivity 6 is not 4 or 8"),
+    (dict(h=1 << 15, w=1 << 16), 2, "h*w"),
+    (dict(st=None), 1, "stencil is NULL"),
+    (dict(count=None), 1, "count is NULL"),
+    (dict(count=FAKE + (1 << 30) + 2), 1, "count is not 4-byte aligned"),
+    (dict(ws=FAKE + (2 << 30) + 16), 1, "workspace is not 256-byte aligned"),
+    (dict(ws_bytes=100), 1, "workspace has 100 bytes"),
+    (dict(count=FAKE + 64), 1, "count overlaps input stencil"),
+    (dict(ws=FAKE + (1 << 30)), 1, "overlaps"),
+])
+def test_dynamic_objects_rejects(kwargs, status, needle):
+    assert dyn(**kwargs) == status
+    assert needle in _capi.last_error(), _capi.last_error()
+
+
+def test_dynamic_objects_empty_batch_and_workspace_size():
+    L = _capi.lib()
+    assert dyn(n=0) == _capi.EXW_SUCCESS
+    assert dyn(n=0, st=None, count=None, ws=None) == _capi.EXW_SUCCESS
+    assert L.exw_dynamic_objects_workspace_bytes(2, 40, 70) == 4 * 2 * 40 * 70
+    assert L.exw_dynamic_objects_workspace_bytes(0, 40, 70) == 0
+    assert L.exw_dynamic_objects_workspace_bytes(2, 0, 70) == 0
