@@ -7,7 +7,10 @@
 // edge or a corner (8-connectivity).
 //
 // Pass 1, one workgroup per 32 x 32 tile: union-find over the tile in LDS.
-// Labels are in-tile indices; a union links the larger root under the
+// Each pixel starts labelled with the first pixel of its run of marked
+// pixels in the row (a wavefront ballot), so only links between rows are
+// made, once per stretch where two rows touch. Labels are in-tile indices;
+// a union links the larger root under the
 // smaller with an LDS atomicMin and retries from the old parent when another
 // lane linked it first, so every label points to a smaller or equal index
 // and every find ends. Each pixel then stores the frame-wide index of its
@@ -99,25 +102,36 @@ __global__ __launch_bounds__(kCcThreads) void cc_tile_kernel(CcArgs a) {
         const int r = row0 + j * (kCcThreads / kCcTile);
         const int x = x0 + col, y = y0 + r;
         mk[j] = x < a.w && y < a.h && st[static_cast<int64_t>(y) * a.w + x] != 0;
-        lab[r * kCcTile + col] = mk[j] ? r * kCcTile + col : -1;
+        // A wavefront holds two whole tile rows (lanes 0..31, 32..63): each
+        // marked pixel starts labelled with the first pixel of its run of
+        // marked pixels in the row, so runs need no links of their own.
+        const unsigned long long both = __ballot(mk[j]);
+        const uint32_t bits = __lane_id() < kCcTile ? static_cast<uint32_t>(both)
+                                                    : static_cast<uint32_t>(both >> kCcTile);
+        const uint32_t gaps = ~bits & ((1u << col) - 1u);  // unmarked pixels left of this one
+        const int start = gaps ? kCcTile - __clz(gaps) : 0;
+        lab[r * kCcTile + col] = mk[j] ? r * kCcTile + start : -1;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kCcRows; ++j) {
-        if (!mk[j]) continue;
         const int r = row0 + j * (kCcThreads / kCcTile);
+        if (!mk[j] || r + 1 >= kCcTile) continue;
         const int i = r * kCcTile + col;
-        // right, below, and for 8-connectivity the two lower diagonals; a
-        // neighbour is marked iff its label is not -1 (labels stay >= 0)
-        if (col + 1 < kCcTile && lds_load(lab + i + 1) >= 0) lds_union(lab, i, i + 1);
-        if (r + 1 < kCcTile) {
-            if (lds_load(lab + i + kCcTile) >= 0) lds_union(lab, i, i + kCcTile);
-            if (a.eight) {
-                if (col > 0 && lds_load(lab + i + kCcTile - 1) >= 0)
-                    lds_union(lab, i, i + kCcTile - 1);
-                if (col + 1 < kCcTile && lds_load(lab + i + kCcTile + 1) >= 0)
-                    lds_union(lab, i, i + kCcTile + 1);
-            }
+        // Links to the row below, made once per stretch where the two rows
+        // touch: below at the stretch's first column (the pixel whose left
+        // and lower-left neighbours are not both marked), a diagonal only
+        // where neither the pixel beside nor the pixel below is marked. A
+        // neighbour is marked iff its label is not -1 (labels stay >= 0).
+        const bool lf = col > 0 && lds_load(lab + i - 1) >= 0;
+        const bool rt = col + 1 < kCcTile && lds_load(lab + i + 1) >= 0;
+        const bool dn = lds_load(lab + i + kCcTile) >= 0;
+        const bool dl = col > 0 && lds_load(lab + i + kCcTile - 1) >= 0;
+        const bool dr = col + 1 < kCcTile && lds_load(lab + i + kCcTile + 1) >= 0;
+        if (dn && !(lf && dl)) lds_union(lab, i, i + kCcTile);
+        if (a.eight) {
+            if (dl && !dn && !lf) lds_union(lab, i, i + kCcTile - 1);
+            if (dr && !dn && !rt) lds_union(lab, i, i + kCcTile + 1);
         }
     }
     __syncthreads();
@@ -157,21 +171,28 @@ __global__ __launch_bounds__(64) void cc_border_kernel(CcArgs a) {
     int x, y;
     if (t < kCcTile) { x = x0 + kCcTile - 1; y = y0 + t; }         // right column
     else { x = x0 + (t - kCcTile); y = y0 + kCcTile - 1; }          // bottom row
+    auto marked = [&](int mx, int my) {
+        return mx >= 0 && mx < a.w && my >= 0 && my < a.h && g_load(lab + my * a.w + mx) >= 0;
+    };
     int joined = 0;
-    if (x < a.w && y < a.h) {
+    if (x < a.w && y < a.h && marked(x, y)) {
         const int p = y * a.w + x;
-        if (g_load(lab + p) >= 0) {
-            auto link = [&](int nx, int ny) {
-                if (nx < 0 || nx >= a.w || ny < 0 || ny >= a.h) return;
-                const int q = ny * a.w + nx;
-                if (g_load(lab + q) >= 0) joined += g_union(lab, p, q);
-            };
-            if (t < kCcTile) {  // across the right border
-                link(x + 1, y);
-                if (a.eight) { link(x + 1, y - 1); link(x + 1, y + 1); }
-            } else {            // across the bottom border
-                link(x, y + 1);
-                if (a.eight) { link(x - 1, y + 1); link(x + 1, y + 1); }
+        auto link = [&](int nx, int ny) { joined += g_union(lab, p, ny * a.w + nx); };
+        // A link that the border's other links imply is skipped (the same
+        // rules as inside the tiles, along the border).
+        if (t < kCcTile) {  // across the right border
+            const bool rn = marked(x + 1, y), up = marked(x, y - 1), ru = marked(x + 1, y - 1);
+            if (rn && !(t > 0 && up && ru)) link(x + 1, y);
+            if (a.eight) {
+                if (ru && !rn && !up) link(x + 1, y - 1);
+                if (!rn && !marked(x, y + 1) && marked(x + 1, y + 1)) link(x + 1, y + 1);
+            }
+        } else {            // across the bottom border
+            const bool dn = marked(x, y + 1), lf = marked(x - 1, y), dl = marked(x - 1, y + 1);
+            if (dn && !(t > kCcTile && lf && dl)) link(x, y + 1);
+            if (a.eight) {
+                if (dl && !dn && !lf) link(x - 1, y + 1);
+                if (!dn && !marked(x + 1, y) && marked(x + 1, y + 1)) link(x + 1, y + 1);
             }
         }
     }
