@@ -10,15 +10,15 @@
 // Each pixel starts labelled with the first pixel of its run of marked
 // pixels in the row (a wavefront ballot), so only links between rows are
 // made, once per stretch where two rows touch. Labels are in-tile indices;
-// a union links the larger root under the
-// smaller with an LDS atomicMin and retries from the old parent when another
-// lane linked it first, so every label points to a smaller or equal index
-// and every find ends. Each pixel then stores the frame-wide index of its
+// a union links the larger root under the smaller with an LDS atomicMin and
+// retries from the old parent when another lane linked it first, so every
+// label points to a smaller or equal index and every find ends. Each pixel then stores the frame-wide index of its
 // tile root, and the tile adds its number of roots to the frame's count.
 // Pass 2, one workgroup per tile: the tile's right column and bottom row are
 // joined to their neighbours across the border with the same union-find in
-// global memory (agent-scope atomics and loads), and every link that joins
-// two sets subtracts one from the count. The count is the number of sets
+// global memory (agent-scope atomics and loads), under the same rules for
+// skipping implied links, and every link that joins two sets subtracts one
+// from the count. The count is the number of sets
 // left whatever the order of the links, so it is exact.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -167,12 +167,15 @@ __global__ __launch_bounds__(64) void cc_border_kernel(CcArgs a) {
     const int x0 = (tile % a.tiles_x) * kCcTile, y0 = (tile / a.tiles_x) * kCcTile;
     const int64_t hw = static_cast<int64_t>(a.h) * a.w;
     int *lab = a.labels + frame * hw;
+    const uint8_t *st = a.stencil + frame * hw;
     const int t = threadIdx.x;
     int x, y;
     if (t < kCcTile) { x = x0 + kCcTile - 1; y = y0 + t; }         // right column
     else { x = x0 + (t - kCcTile); y = y0 + kCcTile - 1; }          // bottom row
+    // (whether a pixel is marked never changes: read from the stencil, which
+    // the caches may serve; only the union-find needs coherent loads)
     auto marked = [&](int mx, int my) {
-        return mx >= 0 && mx < a.w && my >= 0 && my < a.h && g_load(lab + my * a.w + mx) >= 0;
+        return mx >= 0 && mx < a.w && my >= 0 && my < a.h && st[my * a.w + mx] != 0;
     };
     int joined = 0;
     if (x < a.w && y < a.h && marked(x, y)) {
