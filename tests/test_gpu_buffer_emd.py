@@ -80,3 +80,23 @@ def test_full_size_gbuffer_normals_bf16():
     got = gpu_emd(cur, prev, -1.0, 1.0, 256, "bf16", dev)
     ref = buffer_emd.buffer_emd(stored(cur, "bf16"), stored(prev, "bf16"), -1.0, 1.0, 256)
     assert np.array_equal(got, ref)
+
+
+def test_plane_at_the_size_limit():
+    """One plane of 2^30 values (the C ABI's limit; 4 GiB per buffer): every
+    value of cur in bin 5 and of prev in bin 2 of 8 on [0, 1] moves all the
+    mass 3 bins, so the EMD is 3 bin widths exactly (closed form); the counts
+    and their cumulative sums reach 2^30."""
+    dev = need_gpu()
+    side = 1 << 15
+    announce("buffer EMD at the size limit", side, side)
+    cur = torch.full((1, 1, side, side), 0.70, dtype=torch.float32, device=dev)   # bin 5
+    prev = torch.full((1, 1, side, side), 0.30, dtype=torch.float32, device=dev)  # bin 2
+    got = exw.buffer_emd(cur, prev, 0.0, 1.0, 8)
+    torch.cuda.synchronize()
+    assert got.cpu().tolist() == [[3 * 0.125]]
+    same = exw.buffer_emd(cur, cur, 0.0, 1.0, 8)
+    torch.cuda.synchronize()
+    assert same.cpu().tolist() == [[0.0]]
+    del cur, prev
+    torch.cuda.empty_cache()

@@ -122,3 +122,22 @@ def test_synthetic_stencils_full_size(index):
     announce("dynamic objects full size", index, st.shape)
     check(st, f"workload {index}", dev)
     assert (dynamic_objects.dynamic_objects(st) >= 1).all()
+
+
+def test_frame_at_the_size_limit():
+    """H * W = 2^30 (32768 x 32768, the C ABI's limit): a grid of 48 x 48
+    squares 16 pixels apart has one object per square in either
+    connectivity, (32768 / 64)^2 = 262144 (closed form; the 1 GiB stencil
+    is built on the GPU)."""
+    dev = need_gpu()
+    side = 1 << 15
+    announce("dynamic objects at the size limit", side, side)
+    r = (torch.arange(side, device=dev) % 64) < 48
+    st = (r[:, None] & r[None, :]).to(torch.uint8)[None]
+    del r
+    for conn in (4, 8):
+        got = exw.dynamic_objects(st, conn)
+        torch.cuda.synchronize()
+        assert got.cpu().tolist() == [(side // 64) ** 2], (conn, got)
+    del st
+    torch.cuda.empty_cache()
