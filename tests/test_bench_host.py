@@ -80,3 +80,49 @@ def test_profile_names_match_symbols():
     assert keys["exw::adjoint_tiles_kernel<__bf16, 12, 1>"] == m
     assert "exw::warp_forward_kernel<half, 4, 3, true, false>" in keys
     assert "exw::stream_copy_kernel" in keys
+
+
+def _counter_csv(path, counter, rows):
+    """A rocprofv3 counter-collection CSV with the columns the summariser reads."""
+    import csv
+    cols = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id",
+            "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size",
+            "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "Counter_Name",
+            "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(cols)
+        for i, (name, value) in enumerate(rows, 1):
+            w.writerow([i, i, "Agent 1", 1, 1, 1, 64, 1, name, 256, 0, 0, 8, 0, 16, counter, value,
+                        0, 1])
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    import json
+    import bench_traffic as bt
+    tiles = "void exw::(anonymous namespace)::adjoint_tiles_kernel<float, 4, 3>(exw::(anonymous namespace)::BwdArgs<float>)"
+    far = "void exw::(anonymous namespace)::adjoint_far_kernel<float, 4, 3>(exw::(anonymous namespace)::BwdArgs<float>, float*)"
+    copy = "void exw::(anonymous namespace)::stream_copy_kernel(float __vector(4) const*, float __vector(4)*, long)"
+    # the copy of 1 GiB reads FETCH = 512 Ki KiB (half of its bytes) and WRITE = 1 Mi KiB;
+    # two dispatches of the tile kernel average 1000 KiB fetched
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE",
+                 [(copy, 524288.0), (tiles, 900.0), (tiles, 1100.0), (far, 10.0)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE",
+                 [(copy, 1048576.0), (tiles, 300.0), (tiles, 300.0), (far, 0.0)])
+    js = tmp_path / "t.json"
+    import sys
+    argv = sys.argv
+    sys.argv = ["bench_traffic.py", "traffic", "--workload", "wl", "--fetch", str(tmp_path / "f.csv"),
+                "--write", str(tmp_path / "w.csv"), "--summary", str(tmp_path / "s.txt"),
+                "--json", str(js), "--command", "x"]
+    try:
+        bt.main()
+    finally:
+        sys.argv = argv
+    e = json.loads(js.read_text())["calls"]["warp_backward|wl"]
+    assert e["fetch_scale"] == 2.0 and e["write_scale"] == 1.0
+    assert e["fetch_bytes_per_launch"] == round((1000.0 + 10.0) * 1024 * 2)
+    assert e["write_bytes_per_launch"] == round(300.0 * 1024)
+    assert e["hbm_bytes_per_launch"] == e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    assert len(e["kernels"]) == 2 and all(k.startswith("_Z") for k in e["kernels"])
+    assert e["code_sha"] == bench.kernel_code_sha(e["kernels"], _lib())
