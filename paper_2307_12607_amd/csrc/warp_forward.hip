@@ -124,9 +124,13 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
     auto row1 = [&](int j) {
         return static_cast<uint32_t>(min(q.y - ry[j] + 1, h - 1)) * static_cast<uint32_t>(w);
     };
-    float ex = 0.0f;
-    if (threadIdx.x < 2 * CT * KT) {
-        const int lq = threadIdx.x;
+    // Lane l < 2CK loads lane 63's right-hand tap of phase l / 2C, row
+    // (l / C) % 2 and channel l % C; the other lanes repeat lane l % 2CK. No
+    // branch around the load: converting a 16-bit value inside one made the
+    // wavefront wait for it before issuing the gathers.
+    T exr;
+    {
+        const int lq = static_cast<int>(threadIdx.x) % (2 * CT * KT);
         const int jq = lq / (2 * CT), rq = (lq / CT) % 2, cq = lq % CT;
         int ryq = ry[0], rxq = rx[0];
 #pragma unroll
@@ -135,7 +139,7 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
         const int rowq = rq ? min(q.y - ryq + 1, h - 1) : q.y - ryq;
         const uint32_t off = static_cast<uint32_t>(rowq) * static_cast<uint32_t>(w) +
                              static_cast<uint32_t>(min(tx0 + kTileW - rxq, w - 1));
-        ex = to_f32(*at(fin, off + static_cast<uint32_t>(cq) * hw32));
+        exr = *at(fin, off + static_cast<uint32_t>(cq) * hw32);
     }
     float a0[KT][CT], a1[KT][CT];
 #pragma unroll
@@ -157,6 +161,7 @@ __device__ __forceinline__ bool all_phases_uniform(const FwdArgs<T> &a, const Pi
             a1[j][ch] = to_f32(*at(fin, o1 + ch * hw32));
         }
     }
+    const float ex = to_f32(exr);
 #pragma unroll
     for (int j = 0; j < KT; ++j) {
         const float w00 = (1.0f - fx[j]) * (1.0f - fy[j]);
@@ -257,28 +262,30 @@ __device__ __forceinline__ void forward_row(const FwdArgs<T> &a, const PixelPos 
                 const uint32_t xe = static_cast<uint32_t>(min(tx0 + kTileW - rx, w - 1));
                 // Lane 63's right-hand taps (2 rows x C channels) are fetched by
                 // lanes 0 .. 2C-1 in one load instruction and read back as
-                // wave-uniform values.
-                float ex = 0.0f;
-                if (threadIdx.x < 2 * CT) {
-                    const int lq = threadIdx.x;
-                    const T *pl = iplane[0];
+                // wave-uniform values; the other lanes repeat lane l % 2C, so
+                // that no load sits in a branch of its own (a 16-bit value
+                // converted there is waited for before the next loads issue),
+                // and the read-backs follow the row loads.
+                const int lq = static_cast<int>(threadIdx.x) % (2 * CT);
+                const T *pl = iplane[0];
 #pragma unroll
-                    for (int ch = 1; ch < CT; ++ch)
-                        if (lq % CT == ch) pl = iplane[ch];
-                    ex = to_f32(*at(pl, (lq < CT ? r0 : r1) + xe));
-                }
-                float e0[CT], e1[CT];
-#pragma unroll
-                for (int ch = 0; ch < CT; ++ch) {
-                    e0[ch] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), ch));
-                    e1[ch] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ex), CT + ch));
-                }
+                for (int ch = 1; ch < CT; ++ch)
+                    if (lq % CT == ch) pl = iplane[ch];
+                const T exr = *at(pl, (lq < CT ? r0 : r1) + xe);
+                T ra0[CT], ra1[CT];
 #pragma unroll
                 for (int ch = 0; ch < CT; ++ch) {
-                    const float a0 = to_f32(*at(iplane[ch], r0 + xa));
-                    const float a1 = to_f32(*at(iplane[ch], r1 + xa));
-                    const float b0 = shift_down1_or(__float_as_int(e0[ch]), a0);
-                    const float b1 = shift_down1_or(__float_as_int(e1[ch]), a1);
+                    ra0[ch] = *at(iplane[ch], r0 + xa);
+                    ra1[ch] = *at(iplane[ch], r1 + xa);
+                }
+                const float ex = to_f32(exr);
+#pragma unroll
+                for (int ch = 0; ch < CT; ++ch) {
+                    const int e0 = __builtin_amdgcn_readlane(__float_as_int(ex), ch);
+                    const int e1 = __builtin_amdgcn_readlane(__float_as_int(ex), CT + ch);
+                    const float a0 = to_f32(ra0[ch]), a1 = to_f32(ra1[ch]);
+                    const float b0 = shift_down1_or(e0, a0);
+                    const float b1 = shift_down1_or(e1, a1);
                     float acc = w00 * a0;
                     acc = fmaf(w01, b0, acc);
                     acc = fmaf(w10, a1, acc);
@@ -291,7 +298,16 @@ __device__ __forceinline__ void forward_row(const FwdArgs<T> &a, const PixelPos 
 #pragma unroll
                 for (int ch = 0; ch < CT; ++ch) {
                     float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
-                    if (valid) {
+                    if constexpr (sizeof(T) == 2) {
+                        // 16-bit: invalid lanes read the plane's first pair
+                        // (in bounds, unused) rather than skip the loads, so
+                        // that no conversion sits in a branch (where it is
+                        // waited for, channel after channel: 4 x 1440p bf16
+                        // 241 -> 231 us, 4K f16 859 -> 830 us; float32 frames
+                        // keep the branch, 1-2 % faster so)
+                        load_pair(at(iplane[ch], valid ? o0 : 0u), a0, b0);
+                        load_pair(at(iplane[ch], valid ? o1 : 0u), a1, b1);
+                    } else if (valid) {
                         load_pair(at(iplane[ch], o0), a0, b0);
                         load_pair(at(iplane[ch], o1), a1, b1);
                     }
@@ -427,16 +443,18 @@ __device__ __forceinline__ bool pair_uniform(const FwdArgs<T> &a, const SegPos &
             const uint32_t r1 =
                 static_cast<uint32_t>(min(y - ry[j] + 1, h - 1)) * static_cast<uint32_t>(w);
             const uint32_t c = static_cast<uint32_t>(x - rx[j]);  // in the row
-            if (threadIdx.x < 2 * CT) {
-                const uint32_t cq = threadIdx.x % CT;
-                const uint32_t ce = static_cast<uint32_t>(min(g.sx0 + kSegPair - rx[j], w - 1));
-                ex = to_f32(*at(fin, cq * hw32 + (threadIdx.x < CT ? r0 : r1) + ce));
-            }
+            // every lane loads (lanes from 2C up repeat lanes C .. 2C-1): a
+            // 16-bit value converted inside a branch would be waited for
+            // before the gathers below are issued
+            const uint32_t cq = threadIdx.x % CT;
+            const uint32_t ce = static_cast<uint32_t>(min(g.sx0 + kSegPair - rx[j], w - 1));
+            const T exr = *at(fin, cq * hw32 + (threadIdx.x < CT ? r0 : r1) + ce);
 #pragma unroll
             for (int ch = 0; ch < CT; ++ch) {
                 load_pair(at(fin, ch * hw32 + r0 + c), s0[ch], t0[ch]);
                 load_pair(at(fin, ch * hw32 + r1 + c), s1[ch], t1[ch]);
             }
+            ex = to_f32(exr);
         }
         if (j == 0) after_first_loads();  // work that overlaps the gathers in flight
         // pixel 2j: taps (s, t); pixel 2j+1: taps (t, next lane's s)
