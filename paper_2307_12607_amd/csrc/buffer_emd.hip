@@ -68,18 +68,22 @@ __global__ __launch_bounds__(kEmdThreads) void emd_hist_kernel(EmdArgs a) {
     const int64_t begin = static_cast<int64_t>(part) * a.run;
     const int64_t end = min(a.hw, begin + a.run);
     for (int64_t i0 = begin + threadIdx.x; i0 < end; i0 += kEmdThreads * kEmdUnroll) {
-        float va[kEmdUnroll], vb[kEmdUnroll];
+        // Coalesced loads, all in flight: past the run's end a thread reads
+        // its last value again (counted nowhere) rather than skip the load,
+        // so that no load, and no 16-bit conversion, sits in a branch (one
+        // there is waited for before the next load issues).
+        T ra[kEmdUnroll], rb[kEmdUnroll];
 #pragma unroll
-        for (int j = 0; j < kEmdUnroll; ++j) {  // coalesced loads, all in flight
-            const int64_t i = i0 + static_cast<int64_t>(j) * kEmdThreads;
-            va[j] = i < end ? to_f32(pa[i]) : 0.0f;
-            vb[j] = i < end ? to_f32(pb[i]) : 0.0f;
+        for (int j = 0; j < kEmdUnroll; ++j) {
+            const int64_t i = min(i0 + static_cast<int64_t>(j) * kEmdThreads, end - 1);
+            ra[j] = pa[i];
+            rb[j] = pb[i];
         }
 #pragma unroll
         for (int j = 0; j < kEmdUnroll; ++j) {
             if (i0 + static_cast<int64_t>(j) * kEmdThreads < end) {
-                atomicAdd(&hist[bin_of(va[j], a.lo, a.scale, a.bins)], 1u);
-                atomicAdd(&hist[a.bins + bin_of(vb[j], a.lo, a.scale, a.bins)], 1u);
+                atomicAdd(&hist[bin_of(to_f32(ra[j]), a.lo, a.scale, a.bins)], 1u);
+                atomicAdd(&hist[a.bins + bin_of(to_f32(rb[j]), a.lo, a.scale, a.bins)], 1u);
             }
         }
     }

@@ -96,12 +96,22 @@ __global__ __launch_bounds__(kCcThreads) void cc_tile_kernel(CcArgs a) {
     const uint8_t *st = a.stencil + frame * hw;
     const int col = threadIdx.x % kCcTile;
     const int row0 = threadIdx.x / kCcTile;  // rows row0 + 8 j
+    // The rows' stencil bytes are loaded first, all in flight (a pixel past
+    // the frame's edge reads the edge pixel and is unmarked): a load inside
+    // the bounds test would be waited for before the next one issues.
     bool mk[kCcRows];
+    uint8_t sv[kCcRows];
+#pragma unroll
+    for (int j = 0; j < kCcRows; ++j) {
+        const int r = row0 + j * (kCcThreads / kCcTile);
+        const int x = min(x0 + col, a.w - 1), y = min(y0 + r, a.h - 1);
+        sv[j] = st[static_cast<int64_t>(y) * a.w + x];
+    }
 #pragma unroll
     for (int j = 0; j < kCcRows; ++j) {
         const int r = row0 + j * (kCcThreads / kCcTile);
         const int x = x0 + col, y = y0 + r;
-        mk[j] = x < a.w && y < a.h && st[static_cast<int64_t>(y) * a.w + x] != 0;
+        mk[j] = x < a.w && y < a.h && sv[j] != 0;
         // A wavefront holds two whole tile rows (lanes 0..31, 32..63): each
         // marked pixel starts labelled with the first pixel of its run of
         // marked pixels in the row, so runs need no links of their own.
@@ -172,30 +182,51 @@ __global__ __launch_bounds__(64) void cc_border_kernel(CcArgs a) {
     int x, y;
     if (t < kCcTile) { x = x0 + kCcTile - 1; y = y0 + t; }         // right column
     else { x = x0 + (t - kCcTile); y = y0 + kCcTile - 1; }          // bottom row
-    // (whether a pixel is marked never changes: read from the stencil, which
-    // the caches may serve; only the union-find needs coherent loads)
-    auto marked = [&](int mx, int my) {
-        return mx >= 0 && mx < a.w && my >= 0 && my < a.h && st[my * a.w + mx] != 0;
-    };
+    // Whether a pixel is marked never changes: it is read from the stencil,
+    // which the caches may serve (only the union-find needs coherent loads).
+    // The six pixels a thread may test are loaded first, all in flight
+    // (clamped to the frame; those outside it are unmarked): a load inside
+    // the tests would be waited for before the next one issues. Right
+    // column: (x, y), (x+1, y), (x, y-1), (x+1, y-1), (x, y+1), (x+1, y+1);
+    // bottom row: (x, y), (x, y+1), (x-1, y), (x-1, y+1), (x+1, y),
+    // (x+1, y+1).
+    const bool rc = t < kCcTile;
+    bool m[6];
+    {
+        uint8_t v[6];
+        int mx[6], my[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int side = k < 2 ? 0 : (k < 4 ? -1 : 1);
+            const int dx = rc ? (k & 1) : side;
+            const int dy = rc ? side : (k & 1);
+            mx[k] = x + dx;
+            my[k] = y + dy;
+            v[k] = st[min(max(my[k], 0), a.h - 1) * a.w + min(max(mx[k], 0), a.w - 1)];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            m[k] = mx[k] >= 0 && mx[k] < a.w && my[k] >= 0 && my[k] < a.h && v[k] != 0;
+    }
     int joined = 0;
-    if (x < a.w && y < a.h && marked(x, y)) {
+    if (m[0]) {
         const int p = y * a.w + x;
         auto link = [&](int nx, int ny) { joined += g_union(lab, p, ny * a.w + nx); };
         // A link that the border's other links imply is skipped (the same
         // rules as inside the tiles, along the border).
-        if (t < kCcTile) {  // across the right border
-            const bool rn = marked(x + 1, y), up = marked(x, y - 1), ru = marked(x + 1, y - 1);
+        if (rc) {  // across the right border
+            const bool rn = m[1], up = m[2], ru = m[3];
             if (rn && !(t > 0 && up && ru)) link(x + 1, y);
             if (a.eight) {
                 if (ru && !rn && !up) link(x + 1, y - 1);
-                if (!rn && !marked(x, y + 1) && marked(x + 1, y + 1)) link(x + 1, y + 1);
+                if (!rn && !m[4] && m[5]) link(x + 1, y + 1);
             }
-        } else {            // across the bottom border
-            const bool dn = marked(x, y + 1), lf = marked(x - 1, y), dl = marked(x - 1, y + 1);
+        } else {   // across the bottom border
+            const bool dn = m[1], lf = m[2], dl = m[3];
             if (dn && !(t > kCcTile && lf && dl)) link(x, y + 1);
             if (a.eight) {
                 if (dl && !dn && !lf) link(x - 1, y + 1);
-                if (!dn && !marked(x + 1, y) && marked(x + 1, y + 1)) link(x + 1, y + 1);
+                if (!dn && !m[4] && m[5]) link(x + 1, y + 1);
             }
         }
     }
