@@ -38,6 +38,16 @@ Two subcommands, each reading the CSV files rocprofv3 wrote:
                          counts in units of 4 cycles)
       with the kernel's VGPRs (from its descriptor) and workgroup size.
 
+  requests --workload "<name>" --csv <counter csv> --summary <txt> --command "<cmd>"
+      per-kernel L1-to-L2 requests from one `rocprofv3 --pmc` run of
+      TCP_TCC_READ_REQ_sum TCP_TCC_READ_REQ_LATENCY_sum TCP_TCC_WRITE_REQ_sum
+      TCP_TOTAL_CACHE_ACCESSES_sum GRBM_GUI_ACTIVE, means over dispatches:
+        mean read latency (cycles)  = TCP_TCC_READ_REQ_LATENCY / TCP_TCC_READ_REQ
+        reads in flight per CU      = TCP_TCC_READ_REQ_LATENCY / (256 * cycles)
+      (the latency counter sums every read's cycles over the device's 256
+      vector L1 caches, so by Little's law it is the mean number of reads
+      outstanding times the cycles elapsed).
+
 Symbol names are matched to the profiler's kernel names with c++filt.
 """
 
@@ -281,6 +291,50 @@ def cmd_counters(a):
     print("\n".join(out))
 
 
+def per_kernel_means(paths):
+    """{kernel key: {counter: mean over dispatches}} of counter CSV files (a
+    dispatch's rows summed per counter)."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    raw = set()
+    rows = []
+    for path in paths:
+        per = collections.defaultdict(float)
+        names = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                d = (int(r["Dispatch_Id"]), r["Counter_Name"])
+                per[d] += float(r["Counter_Value"])
+                names[d] = r["Kernel_Name"]
+        for (disp, ctr), v in per.items():
+            rows.append((names[(disp, ctr)], ctr, v))
+            raw.add(names[(disp, ctr)])
+    keys = dict(zip(sorted(raw), demangle(sorted(raw))))
+    for name, ctr, v in rows:
+        vals[keys[name]][ctr].append(v)
+    return {k: {c: mean(v) for c, v in m.items()} for k, m in vals.items()}
+
+
+def cmd_requests(a):
+    means = per_kernel_means(a.csv)
+    out = [f"# rocprofv3 L1-to-L2 requests per dispatch (mean over dispatches), {a.workload}"]
+    out += [f"# command: {c}" for c in a.command]
+    out.append("# summed over the device's 256 vector L1 caches; definitions in bench_traffic.py")
+    out.append(f"\n{'kernel':76s} {'reads':>9s} {'writes':>9s} {'read latency':>13s} "
+               f"{'reads in flight':>16s}")
+    out.append(f"{'':76s} {'(M)':>9s} {'(M)':>9s} {'(cycles)':>13s} {'(per CU)':>16s}")
+    for k in sorted(means, key=lambda k: -means[k].get("GRBM_GUI_ACTIVE", 0.0)):
+        if not k.startswith("exw::"):
+            continue
+        m = means[k]
+        cyc = m["GRBM_GUI_ACTIVE"] / 8.0
+        rd, lat = m["TCP_TCC_READ_REQ_sum"], m["TCP_TCC_READ_REQ_LATENCY_sum"]
+        out.append(f"{k[:76]:76s} {rd / 1e6:9.2f} {m['TCP_TCC_WRITE_REQ_sum'] / 1e6:9.2f} "
+                   f"{lat / max(rd, 1.0):13.0f} {lat / (256 * cyc):16.1f}")
+    with open(a.summary, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     p = argparse.ArgumentParser()
     sub = p.add_subparsers(dest="cmd", required=True)
@@ -301,8 +355,14 @@ def main():
     c.add_argument("--csv", action="append", required=True)
     c.add_argument("--summary", required=True)
     c.add_argument("--command", action="append", default=[])
+    q = sub.add_parser("requests")
+    q.add_argument("--workload", required=True)
+    q.add_argument("--csv", action="append", required=True)
+    q.add_argument("--summary", required=True)
+    q.add_argument("--command", action="append", default=[])
     a = p.parse_args()
-    {"trace": cmd_trace, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"trace": cmd_trace, "traffic": cmd_traffic, "counters": cmd_counters,
+     "requests": cmd_requests}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -126,3 +126,47 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     assert e["hbm_bytes_per_launch"] == e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
     assert len(e["kernels"]) == 2 and all(k.startswith("_Z") for k in e["kernels"])
     assert e["code_sha"] == bench.kernel_code_sha(e["kernels"], _lib())
+
+
+def test_request_summary_applies_littles_law(tmp_path):
+    """Reads in flight per CU = summed read latency / (256 caches * kernel
+    cycles), the kernel cycles being GRBM_GUI_ACTIVE over the 8 XCDs; the
+    mean latency = summed latency / reads. Two dispatches are averaged."""
+    import csv
+    import bench_traffic as bt
+    fwd = "void exw::(anonymous namespace)::warp_forward_kernel<float, 4, 3, true, false>(exw::(anonymous namespace)::FwdArgs<float>)"
+    cols = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id",
+            "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size",
+            "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count", "Counter_Name",
+            "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    # dispatch 1: 1000 cycles per XCD, 2e6 reads of 500 cycles each; dispatch 2: the
+    # same cycles, 4e6 reads of 500 cycles (the latency counter is split over two rows)
+    per = {1: {"GRBM_GUI_ACTIVE": [8000.0], "TCP_TCC_READ_REQ_sum": [2e6],
+               "TCP_TCC_READ_REQ_LATENCY_sum": [1e9], "TCP_TCC_WRITE_REQ_sum": [1e6],
+               "TCP_TOTAL_CACHE_ACCESSES_sum": [5e6]},
+           2: {"GRBM_GUI_ACTIVE": [8000.0], "TCP_TCC_READ_REQ_sum": [4e6],
+               "TCP_TCC_READ_REQ_LATENCY_sum": [1.5e9, 0.5e9], "TCP_TCC_WRITE_REQ_sum": [3e6],
+               "TCP_TOTAL_CACHE_ACCESSES_sum": [5e6]}}
+    path = tmp_path / "r.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(cols)
+        for disp, ctrs in per.items():
+            for ctr, values in ctrs.items():
+                for v in values:
+                    w.writerow([disp, disp, "Agent 1", 1, 1, 1, 64, 1, fwd, 256, 0, 0, 8, 0, 16,
+                                ctr, v, 0, 1])
+    import sys
+    argv = sys.argv
+    sys.argv = ["bench_traffic.py", "requests", "--workload", "wl", "--csv", str(path),
+                "--summary", str(tmp_path / "s.txt"), "--command", "x"]
+    try:
+        bt.main()
+    finally:
+        sys.argv = argv
+    line = next(l for l in (tmp_path / "s.txt").read_text().splitlines()
+                if l.startswith("exw::warp_forward_kernel"))
+    reads, writes, latency, in_flight = (float(v) for v in line.split()[-4:])
+    assert reads == 3.0 and writes == 2.0          # millions, mean of the two dispatches
+    assert latency == 500.0                        # 1.5e9 / 3e6
+    assert abs(in_flight - 1.5e9 / (256 * 1000.0)) < 0.05
