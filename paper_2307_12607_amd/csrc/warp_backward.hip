@@ -992,7 +992,8 @@ int tile_rows_for(int c) {
     // segment at TH = 2, 2.9 at TH = 3, 2.5 at TH = 4 on workload 2) but hold
     // more LDS per wavefront; measured on workload 2, TH = 3 is fastest for
     // float32 and 16-bit frames with up to four channels (TH = 2 and TH = 4
-    // were slower in both).
+    // were slower in both), and on three-channel frames under i.i.d. motion
+    // (8 x 1080p: 634-649 us against 780, 676 and 774 at TH = 2, 4, 6).
     return c <= 4 ? 3 : 2;
 }
 
