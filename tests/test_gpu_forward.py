@@ -172,6 +172,32 @@ def test_non_finite_huge_and_denormal_motion():
         compare_with_exact(out, mask, ex, ex_mask, mv, phases, "f32", f"specials {phases}")
 
 
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_non_finite_huge_and_denormal_motion_16bit(dtype):
+    """The same special motion values on 16-bit frames of 1, 3, 4 and 12
+    channels: the one-pixel paths load for invalid lanes too (the plane's
+    first pair, unused), and those lanes must still come out 0 and unmasked."""
+    dev = need_gpu()
+    h, w = 6, 70
+    specials = np.array([np.nan, np.inf, -np.inf, 1e30, -1e30, 3e38, 1e-40, -1e-40, 1e-45,
+                         -0.0, 0.0, 69.0, -69.0, 70.0, 5.0, -5.0], np.float32)
+    rng = np.random.default_rng(16)
+    for c in (1, 3, 4, 12):
+        src = rng.random((2, c, h, w), dtype=np.float32)
+        mv = np.stack([rng.choice(specials, (2, h, w)), rng.choice(specials, (2, h, w))], axis=1)
+        mv = mv.astype(np.float32)
+        for phases in ([1.0], [0.5, 0.75], [-1.0, 2.0, 0.25, 1.0]):
+            announce("specials 16-bit", dtype, c, phases)
+            out, mask, cnt = run_forward(src, mv, phases, dtype, dev)
+            ref, ref_mask, ref_cnt = warp_oracle.forward(stored(src, dtype), mv, phases)
+            assert np.array_equal(mask, ref_mask), (c, phases)
+            assert np.array_equal(cnt, ref_cnt)
+            assert np.isfinite(out).all()
+            invalid = np.broadcast_to((mask == 0)[:, :, None], out.shape)
+            assert (out[invalid] == 0).all(), (c, phases)
+            assert_close_kernel(out, ref, dtype, f"specials {dtype} c={c} {phases}")
+
+
 def test_three_quarter_phase_at_the_bounds_exact_vs_rounded():
     """Motions whose product with the phase 3/4 lies within an ulp of a frame
     bound: the GPU decides validity on the float32-rounded displacement, so
