@@ -96,7 +96,9 @@ const char *exw_last_error(void);
  *   phases: host array of k finite floats (s = i/4 in the method; any finite
  *           value is accepted, 0 gives the identity).
  *   k: 1..EXW_MAX_PHASES.   n >= 0, 1 <= c <= EXW_MAX_CHANNELS, h, w >= 0,
- *   h*w <= 2^30.
+ *   h*w <= 2^30. Larger batches than the launch grids hold (below 2^31
+ *   tiles of 64 x 4 pixels; for twelve 16-bit channels also below 2^31 row
+ *   segments of 128 pixels, counting rows in fours) are EXW_ERROR_UNSUPPORTED.
  *   mask: optional [N,K,H,W] uint8 output, or NULL.
  *   invalid_count: optional [N,K] uint32 output (number of invalid pixels
  *           per frame and phase, paper §III-C holes statistic restricted to

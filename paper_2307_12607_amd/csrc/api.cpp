@@ -109,6 +109,14 @@ exw_status check_common(exw_dtype dtype, int32_t n, int32_t c, int32_t h, int32_
     const uint64_t tiles = uint64_t(n) * ((uint64_t(w) + 63) / 64) * ((uint64_t(h) + 3) / 4);
     if (tiles >= (uint64_t(1) << 31))
         return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu tiles)", (unsigned long long)tiles);
+    // Twelve 16-bit channels run the forward with one workgroup per 128-pixel
+    // row segment: that grid must fit as well.
+    if (c == 12 && dtype != EXW_F32 && w >= 2) {
+        const uint64_t segs = uint64_t(n) * ((uint64_t(w) + 127) / 128) * (((uint64_t(h) + 3) / 4) * 4);
+        if (segs >= (uint64_t(1) << 31))
+            return fail(EXW_ERROR_UNSUPPORTED, "batch too large (%llu row segments)",
+                        (unsigned long long)segs);
+    }
     ck->empty = (n == 0 || h == 0 || w == 0);
     ck->shape.n = n;
     ck->shape.c = c;

@@ -95,6 +95,9 @@ INVALID, UNSUPPORTED = _capi.EXW_ERROR_INVALID_VALUE, _capi.EXW_ERROR_UNSUPPORTE
     (dict(h=1 << 24, w=1), UNSUPPORTED, "2^24"),
     (dict(h=1 << 16, w=1 << 15), UNSUPPORTED, "2^30"),
     (dict(n=1 << 20, c=64, h=4096, w=4096, k=1), UNSUPPORTED, "too large"),
+    # twelve 16-bit channels: 129 * (2^22 - 1) * 4 >= 2^31 row segments, while the
+    # 64 x 4 tiles (129 * (2^22 - 1)), H*W and the element count are in range
+    (dict(dtype=1, n=129, c=12, h=(1 << 24) - 4, w=2), UNSUPPORTED, "row segments"),
 ])
 def test_forward_rejects(kwargs, status, needle):
     st = fwd(**kwargs)
