@@ -267,7 +267,7 @@ def test_backward_shapes_channels_and_partial_requests():
         mv = rng.uniform(-3, 3, (n, 2, h, w)).astype(np.float32)
         phases = [0.25, 0.5, 0.75, 1.0][:k]
         g = rng.standard_normal((n, k, c, h, w)).astype(np.float32)
-        for dtype in ("f32", "bf16"):
+        for dtype in ("f32", "f16", "bf16"):
             announce("backward shapes", n, c, h, w, k, dtype)
             ref_gs, ref_gm = warp_oracle.backward(stored(src, dtype), mv, phases, stored(g, dtype))
             gs, gm = grads_gpu(src, mv, phases, g, dtype, dev)
