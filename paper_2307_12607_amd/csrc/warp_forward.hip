@@ -8,9 +8,10 @@
 // per-(frame, phase) invalid counts.
 //
 // Layout of the work: a wavefront per 128 consecutive pixels of a row, four
-// wavefronts per 128 x 4 tile, tiles renumbered per XCD. The motion vector is
-// read once for all K phases; motion, output and mask accesses are
-// coalesced; the taps of neighbouring lanes fall on neighbouring addresses
+// wavefronts per 128 x 4 tile (a workgroup, or four consecutive workgroups of
+// one wavefront for twelve 16-bit channels), tiles renumbered per XCD. The
+// motion vector is read once for all K phases; motion, output and mask
+// accesses are coalesced; the taps of neighbouring lanes fall on neighbouring addresses
 // wherever the motion is locally smooth. A segment whose 128 pixels share one
 // integer tap offset per phase takes two pixels per lane (two-element loads
 // and stores plus a lane shift); otherwise each 64-pixel half runs the
